@@ -1,0 +1,45 @@
+"""Plain, slow, CPU FP64 oracle for in-situ snapshot reduction.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library, its
+C ABI and the Python binding in ``paper_2407_20731_amd``) imports, links or
+executes anything in this package.  Only ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py`` may use it.  It shares no code,
+tables or constants with the GPU path: every table here is computed from the
+mathematics with mpmath and exact rationals.
+
+What it computes (arXiv 2407.20731, Sec. IV-B): the physics-based, JPEG-like
+lossy reduction of a spectral-element (SEM) velocity snapshot -- keep the
+Legendre coefficients of the most energetic motions, drop the rest, under a
+relative L2 error bound -- as one data-parallel pass over the elements:
+
+  * ``tables``    GLL nodes/weights, Legendre Vandermonde V, its inverse A,
+                  discrete norms gamma, and the tensor tables w3, g3, each the
+                  correctly rounded FP64 value of the exact quantity
+                  (textbook SEM, Deville et al., the SEM reference of Sec. IV-A).
+  * ``exact``     correctly rounded exact sums of FP64 terms (order free).
+  * ``transform`` per-element sum-factorised forward (nodal -> modal) and
+                  inverse transforms in a fixed evaluation order, no FMA.
+  * ``compress``  mass-weighted norm, per-coefficient energies, the global
+                  value threshold that enforces the bound, kept sets, the
+                  compacted blob arrays, reconstruction, the error check and
+                  the rounding repair.
+
+Pins (what each function is checked against, in ``tests/test_oracle_*.py``):
+closed-form GLL rules, scipy's Gauss-Jacobi roots, quadrature exactness,
+numpy's Legendre evaluator, unit coefficients of pure Legendre fields, exact
+keep-all round trip, discrete Parseval, math.fsum / Fraction sums, and brute
+force over all subsets on tiny inputs.  No function here is "parity unpinned".
+"""
+
+from .tables import gll_tables, Tables  # noqa: F401
+from .exact import exact_sum, exact_sum_fraction, rn_leq  # noqa: F401
+from .transform import forward, inverse  # noqa: F401
+from .compress import (  # noqa: F401
+    OracleComponent,
+    OracleResult,
+    compress,
+    decompress,
+    energies,
+    norm_terms,
+    threshold,
+)
