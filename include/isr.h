@@ -1,0 +1,228 @@
+/*
+ * isr.h -- in-situ snapshot reduction on MI355X (gfx950): the C ABI.
+ *
+ * The operation (arXiv 2407.20731, Sec. IV-B, "Turbulence with data
+ * compression"): while a spectral-element (SEM) velocity snapshot is still in
+ * GPU memory, reduce it with the physics-based, JPEG-inspired lossy step --
+ * keep only the Legendre coefficients of the most energetic motions and drop
+ * the rest under a maximal allowed error.  Per velocity component the library
+ *
+ *   1. transforms every hexahedral element's GLL nodal values u[k][j][i] to
+ *      Legendre coefficients c[r][q][p] (tensor product of A = V^-1, with
+ *      V[i][k] = P_k(xi_i) at the Gauss-Lobatto-Legendre nodes xi),
+ *   2. forms the GLL mass-weighted norm U2 = sum_e sum_kji (J_e w_k w_j w_i) u^2
+ *      and the coefficient energies e = (J_e g_r g_q g_p) c^2 (g = discrete
+ *      GLL norms of the Legendre polynomials: 2/(2k+1), and 2/N for k = N),
+ *   3. finds the global value threshold tau, the largest energy value such
+ *      that the dropped energy S(tau) = RN(exact sum of energies < tau) does
+ *      not exceed B = (tol*tol)*U2 (FP64, exact sums, no sort),
+ *   4. compacts the kept coefficients (e >= tau) into a blob: a bitmap, a
+ *      per-element offset table and the kept values,
+ *   5. inverse-transforms the kept set and measures the relative
+ *      mass-weighted L2 error sqrt(err2/U2); if rounding pushed it above tol,
+ *      it lowers B by (tol/rel)^2 * (1 - 2^-20) and repeats 3-5 (at most 4
+ *      times; then ISR_ETOL).
+ *
+ * All sums that decide the threshold (U2, S, err2) are the correctly rounded
+ * values of the exact sums of their FP64 terms, so results do not depend on
+ * scheduling.  With ISR_PREC_FP64 the transforms use one fixed evaluation
+ * order (see isr_forward), so every coefficient, energy and threshold is
+ * reproducible bit for bit by a CPU implementation of the same definition.
+ *
+ * Conventions
+ *   - Every function returns an int status (ISR_OK or a negative ISR_E*),
+ *     except isr_last_error and isr_blob_free.  On error, output handles are
+ *     set to NULL and isr_last_error() describes the failure.
+ *   - "device pointer" = memory on the context's GPU (hipMalloc, or a torch
+ *     CUDA tensor's data_ptr()).  The library never frees caller memory.
+ *   - Streams are hipStream_t passed as void*; NULL = the default stream.
+ *   - A context serialises its own calls and may be used from several host
+ *     threads.  No C++ exception crosses this ABI.
+ */
+#ifndef ISR_H
+#define ISR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define ISR_OK 0
+#define ISR_PENDING 1       /* isr_poll: request not finished yet */
+#define ISR_EINVAL (-1)     /* bad argument (see each call) or non-finite field */
+#define ISR_ENOMEM (-2)     /* footprint above the HBM budget, or allocation failed */
+#define ISR_EDEVICE (-3)    /* a HIP call failed */
+#define ISR_ETOL (-4)       /* error bound not met after the rounding repair */
+#define ISR_ECANCELED (-5)
+#define ISR_ENOTFOUND (-6)  /* unknown request id */
+
+/* ---- precisions of the transforms ------------------------------------- */
+#define ISR_PREC_FP64 0   /* VALU FP64, fixed order, no FMA: bit-exact */
+#define ISR_PREC_FP32 1   /* FP32 MFMA, FP32 accumulation; FP64 norms/select */
+#define ISR_PREC_BF16 2   /* BF16 MFMA (split operands), FP32 accumulation */
+
+/* ---- context flags ---------------------------------------------------- */
+#define ISR_FLAG_TIMING 1u  /* record device time per phase into isr_stats */
+
+#define ISR_MAX_COMP 8
+#define ISR_MAX_ORDER 15
+#define ISR_NPHASE 8
+
+typedef struct isr_ctx isr_ctx;
+typedef struct isr_blob isr_blob;
+
+typedef struct {
+  int32_t device;            /* HIP device ordinal */
+  uint32_t flags;            /* ISR_FLAG_* */
+  uint64_t hbm_budget_bytes; /* cap on device memory the library holds; 0 = 64 GiB */
+  int32_t max_inflight;      /* isr_submit: requests resident at once; 0 = 8 */
+  int32_t reserved;
+  const char *autotune_path; /* optional tile table written by the autotuner; NULL = built in */
+} isr_config;
+
+/* One snapshot to compress.
+ *   field        DEVICE pointer, FP64.  Component c, element e, node (k, j, i)
+ *                is field[c * comp_stride + e * n^3 + (k * n + j) * n + i],
+ *                n = order + 1 (element-local SEM storage, i fastest, shared
+ *                face nodes duplicated).  Must be 8-byte aligned (16-byte
+ *                aligned tiles are read with 16-byte loads).  Borrowed:
+ *                it must stay unchanged until isr_compress returns or
+ *                isr_poll reports completion.  All values must be finite.
+ *   n_elem       number of elements, >= 1, and n_elem * n^3 < 2^32.
+ *   order        polynomial order N in [1, ISR_MAX_ORDER].
+ *   ncomp        velocity components in [1, ISR_MAX_COMP]; each gets its own
+ *                threshold (per-component relative bound).
+ *   comp_stride  values between components; 0 means n_elem * n^3.
+ *   tol          relative mass-weighted L2 bound per component, >= 0; a
+ *                negative tol keeps every coefficient (lossless transform).
+ *   precision    ISR_PREC_*.
+ *   elem_jac     optional DEVICE pointer to n_elem positive FP64 Jacobians of
+ *                affine elements (constant per element); NULL means 1.
+ *   stream       hipStream_t on which `field` was produced; the library's
+ *                work is ordered after it.
+ */
+typedef struct {
+  const double *field;
+  int64_t n_elem;
+  int32_t order;
+  int32_t ncomp;
+  int64_t comp_stride;
+  double tol;
+  int32_t precision;
+  int32_t reserved;
+  const double *elem_jac;
+  void *stream;
+} isr_field;
+
+/* Per-result statistics (arrays are per component). */
+typedef struct {
+  double norm2[ISR_MAX_COMP];    /* U2 */
+  double budget[ISR_MAX_COMP];   /* B actually used (after any repair) */
+  double tau[ISR_MAX_COMP];      /* threshold; +inf = nothing kept; 0 = all kept */
+  double dropped[ISR_MAX_COMP];  /* S(tau) */
+  double err2[ISR_MAX_COMP];     /* measured mass-weighted squared error */
+  double rel_err[ISR_MAX_COMP];  /* sqrt(err2 / U2), 0 when U2 == 0 */
+  uint64_t kept[ISR_MAX_COMP];
+  uint64_t in_bytes;             /* ncomp * n_elem * n^3 * 8 */
+  uint64_t blob_bytes;           /* serialized blob size */
+  double cr;                     /* (in_bytes - blob_bytes) / in_bytes */
+  double t_submit, t_start, t_done; /* host monotonic seconds */
+  float phase_ms[ISR_NPHASE];    /* ISR_FLAG_TIMING: device ms per phase:
+                                    0 norm+histogram pass, 1 threshold select,
+                                    2 candidate pass, 3 refine, 4 compact+verify
+                                    pass, 5 finalize, 6 repair total, 7 unused */
+  int32_t repair_iters;
+  int32_t status;
+  int32_t precision;
+  int32_t reserved;
+} isr_stats;
+
+/* Create a context on cfg->device (cfg may be NULL: device 0, defaults).
+ * Computes the GLL/Legendre tables on the host for every order and uploads
+ * them.  Errors: ISR_EINVAL, ISR_EDEVICE. */
+int isr_create(const isr_config *cfg, isr_ctx **out);
+
+/* Destroy a context: waits for its requests, frees its device memory.  Blobs
+ * of this context must be freed first. */
+int isr_destroy(isr_ctx *ctx);
+
+/* Text of the last error on the calling thread (valid until its next call). */
+const char *isr_last_error(void);
+
+/* Compress one snapshot and wait for the result.  On ISR_OK or ISR_ETOL,
+ * *out receives a device-resident blob owned by the caller (isr_blob_free);
+ * with ISR_ETOL the blob's measured error exceeds tol.  st may be NULL.
+ * Errors: ISR_EINVAL (null/misaligned pointer, order, n_elem, ncomp, NaN
+ * tol, bad precision, non-finite field values), ISR_ENOMEM, ISR_EDEVICE. */
+int isr_compress(isr_ctx *ctx, const isr_field *f, isr_blob **out, isr_stats *st);
+
+/* Compress several snapshots (orders may differ) in one batched launch
+ * sequence.  outs[i] / st[i] as in isr_compress; returns the first non-OK
+ * status (each st[i].status holds its own).  Footprint of the whole batch must
+ * fit the budget (ISR_ENOMEM otherwise). */
+int isr_compress_batch(isr_ctx *ctx, const isr_field *fs, int32_t count, isr_blob **outs,
+                       isr_stats *st);
+
+/* Queue a snapshot for compression and return at once with a request id.
+ * Requests are admitted to the device while their footprint fits the HBM
+ * budget and fewer than max_inflight are resident; later arrivals join the
+ * running ones (continuous batching).  The field must stay unchanged until
+ * isr_poll reports completion.  Errors as isr_compress (argument checks
+ * only; ISR_ENOMEM if the request alone exceeds the budget). */
+int isr_submit(isr_ctx *ctx, const isr_field *f, uint64_t *req);
+
+/* Poll a request: ISR_PENDING while running; otherwise the request's final
+ * status (ISR_OK, ISR_ETOL, or an error) with *out / *st filled, and the
+ * request id is retired.  wait_ms > 0 blocks up to that long; < 0 blocks
+ * until done.  ISR_ENOTFOUND for an unknown or retired id. */
+int isr_poll(isr_ctx *ctx, uint64_t req, int32_t wait_ms, isr_blob **out, isr_stats *st);
+
+/* Reconstruct the nodal field from a blob into d_out (DEVICE, same layout as
+ * the input with comp_stride = n_elem * n^3), FP64 (out_prec ISR_PREC_FP64)
+ * or FP32 (ISR_PREC_FP32).  Uses the FP64 inverse transform in the fixed
+ * order (kept values are widened to FP64 first).  Enqueued on `stream`; the
+ * call returns after enqueueing.  Errors: ISR_EINVAL, ISR_EDEVICE. */
+int isr_decompress(isr_ctx *ctx, const isr_blob *b, void *d_out, int32_t out_prec, void *stream);
+
+/* Forward transform only (no truncation): coefficients c[comp][e][r][q][p]
+ * (p fastest) into d_coef (DEVICE, FP64 for ISR_PREC_FP64, else FP32), in
+ * the requested precision.  FP64 order: t1 = sum_i A[p][i] u[k][j][i], then
+ * t2 = sum_j A[q][j] t1[k][j][p], then c = sum_k A[r][k] t2[k][q][p], each
+ * sum started from its first product and accumulated in ascending index with
+ * separately rounded multiply and add.  Synchronous. */
+int isr_forward(isr_ctx *ctx, const isr_field *f, void *d_coef);
+
+/* Blob queries and (de)serialisation.  Serialized layout (little endian):
+ *   "ISR1", u32 version=1, i32 order, i32 ncomp, i64 n_elem, i32 value_bytes
+ *   (8 or 4), i32 words_per_elem W = ceil(n^3/64), f64 tol, i32 precision,
+ *   i32 status; then per component: f64 U2, B, tau, dropped, err2, rel_err,
+ *   u64 kept, u64 values_offset; then all bitmaps [ncomp][n_elem][W] u64 (bit
+ *   f = p + n q + n^2 r of element e set iff kept), all offset tables
+ *   [ncomp][n_elem + 1] u64 (per component, starting at 0), all kept values
+ *   (component after component, element then f ascending). */
+int isr_blob_info(const isr_blob *b, int32_t *order, int32_t *ncomp, int64_t *n_elem,
+                  int32_t *value_bytes);
+int isr_blob_size(const isr_blob *b, uint64_t *bytes);
+int isr_blob_to_host(const isr_blob *b, void *buf, uint64_t cap);
+int isr_blob_from_host(isr_ctx *ctx, const void *buf, uint64_t n, isr_blob **out);
+void isr_blob_free(isr_blob *b);
+
+/* Host-only: the library's own FP64 tables for order N (each entry the
+ * correctly rounded value of the exact quantity): xi[n], w[n], V[n*n]
+ * (V[i*n+k] = P_k(xi_i)), A[n*n] (A[p*n+i] = (V^-1)[p][i]), gamma[n],
+ * w3[n^3] (w3[(k*n+j)*n+i] = w_k w_j w_i), g3[n^3] (gamma_r gamma_q gamma_p).
+ * Any pointer may be NULL.  No GPU needed.  Errors: ISR_EINVAL. */
+int isr_gll_tables(int32_t order, double *xi, double *w, double *V, double *A, double *gamma,
+                   double *w3, double *g3);
+
+/* Library version string. */
+const char *isr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISR_H */

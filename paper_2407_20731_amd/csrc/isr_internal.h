@@ -1,0 +1,134 @@
+// Internal definitions shared by the HIP kernels and the host runtime.
+// Nothing here is part of the public ABI (include/isr.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace isr {
+
+typedef unsigned long long u64;
+typedef unsigned int u32;
+
+// ---- exact sums of non-negative FP64 terms ------------------------------
+// A term v = sig * 2^(max(E,1) - 1075) (E = biased exponent field, sig = 53-bit
+// significand with its implicit bit) is kept as an integer in units of 2^-1075
+// ("X units"): X(v) = sig << max(E,1).  Terms are binned by E; a bin stores
+// the count and the exact sum of its significands split as hi * 2^21 + lo,
+// hi summing sig >> 21 (< 2^32) and lo summing sig & (2^21 - 1).  Bin 2047
+// (Inf/NaN) only ever counts, and flags a non-finite input.
+constexpr int HBINS = 2048;
+struct HistBin {
+  u64 cnt, lo, hi;
+};
+
+// LDS window of exponent bins held by one workgroup (values outside go
+// straight to the global bins).
+constexpr int WIN = 256;
+constexpr int WIN_HEAD = 16;  // bins kept above the first tile's largest exponent
+
+// Refinement of the threshold inside the boundary exponent bin: the 52
+// fraction bits are resolved 12 at a time (bits 51..40, 39..28, 27..16,
+// 15..4), then 4 (bits 3..0).  Levels are numbered 2..6; level 1 is the
+// exponent.
+constexpr int RBINS = 4096;
+constexpr int NLEV = 6;
+constexpr int CAP = 4096;  // a sub-bin with at most CAP members is resolved by sorting
+
+__host__ __device__ constexpr int level_shift(int L) { return L == 6 ? 0 : 40 - 12 * (L - 2); }
+__host__ __device__ constexpr int level_bits(int L) { return L == 6 ? 4 : 12; }
+
+// Per-component selection state, written by the select kernels.
+struct alignas(256) CompState {
+  u64 P1[64];         // exact sum (X units) of all energies below the boundary bin
+  double U2, B, tau, dropped, err2, rel;
+  double tol;
+  u64 n_values;       // values in this component
+  u64 kept;           // final kept count
+  u64 kept_above;     // energies above the current bin / sub-bin
+  u64 key_prefix;     // bits fixed so far (of the FP64 pattern of tau)
+  u64 key_mask;
+  u64 cur_count;      // members of the current bin / sub-bin
+  u64 r_lo, r_hi;     // 128-bit slack, in significand units of the boundary bin
+  u64 w_lo, w_hi;     // 128-bit significand sum dropped inside the boundary bin
+  u64 list_count[2];  // candidate list fill levels
+  int32_t bstar;      // boundary exponent bin, -1 when tau is +inf or 0
+  int32_t level;      // last level decided
+  int32_t resolved;   // tau final
+  int32_t flags;      // ST_* below
+  int32_t repair;     // host: B was overridden
+  int32_t pad[3];
+};
+
+enum : int32_t {
+  ST_NONFINITE = 1,   // Inf/NaN in the field
+  ST_OVERFLOW = 2,    // an energy or norm term overflowed FP64
+  ST_SPIN = 4,        // a bounded wait expired (should never happen)
+  ST_LIST = 8,        // a candidate list overflowed its capacity
+};
+
+struct DevTables {
+  const double* A;    // [n][n]  A[p][i]
+  const double* V;    // [n][n]  V[i][k]
+  const double* w3;   // [n][n][n]
+  const double* g3;   // [n][n][n]
+  const float* A32;   // FP32 roundings (mixed paths)
+  const float* V32;
+};
+
+// Everything one compression needs on the device.
+struct Job {
+  const double* u;     // field
+  const double* jac;   // per-element Jacobian or null
+  long long comp_stride;
+  long long n_elem;
+  int order;
+  int ncomp;
+  int precision;
+  int vbytes;          // 8 (FP64 values) or 4
+  double tol;
+  double Bov[8];       // per-component budget override (repair); < 0 = none
+  DevTables tab;
+  // scratch
+  HistBin* histE;      // [ncomp][HBINS]  energies
+  HistBin* histN;      // [ncomp][HBINS]  norm terms
+  HistBin* histR;      // [ncomp][HBINS]  error terms
+  HistBin* histL;      // [NLEV-1][ncomp][RBINS]  refinement levels 2..6
+  CompState* st;       // [ncomp]
+  u64* lists;          // [ncomp][2][list_cap]
+  u64 list_cap;
+  u64* lookback;       // [ncomp][tiles]
+  u32* ticket;         // [4]
+  // blob (device)
+  u64* bitmap;         // [ncomp][n_elem][W]
+  u64* elem_ptr;       // [ncomp][n_elem + 1]
+  void* values;        // kept values, component after component
+  u64* voff;           // [ncomp] offset of each component's first value
+};
+
+// Host launchers (kernels are in isr_kernels.hip).
+int tiles_per_comp(int order, long long n_elem);
+int words_per_elem(int order);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_pass1(const Job& j, int grid_x, hipStream_t s);
+hipError_t launch_select1(const Job& j, hipStream_t s);
+hipError_t launch_pass2(const Job& j, int grid_x, hipStream_t s);
+hipError_t launch_refine(const Job& j, int level, int grid_x, hipStream_t s);
+hipError_t launch_select(const Job& j, int level, hipStream_t s);
+hipError_t launch_pass3(const Job& j, int grid, hipStream_t s);
+hipError_t launch_finalize(const Job& j, hipStream_t s);
+hipError_t launch_decompress(const Job& j, void* out, int out_fp64, int grid, hipStream_t s);
+hipError_t launch_forward(const Job& j, void* coef, int grid, hipStream_t s);
+
+// Host tables (isr_tables.cpp): correctly rounded FP64 values.
+struct HostTables {
+  int N;
+  double xi[16], w[16], gamma[16];
+  double V[256], A[256];
+  double w3[4096], g3[4096];
+};
+bool host_tables(int N, HostTables* t);
+
+}  // namespace isr

@@ -1,0 +1,821 @@
+// Host runtime behind the C ABI (include/isr.h): contexts, the HBM arena,
+// the compression pipeline, blobs, decompression and the request queue.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "isr.h"
+#include "isr_internal.h"
+#include "isr_sched.h"
+
+using namespace isr;
+
+// ---------------------------------------------------------------------------
+// errors
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return fail(ISR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+static double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------------------
+// arena: device sub-allocator over large hipMalloc chunks, capped by a budget
+
+namespace isr {
+
+Arena::Arena(uint64_t budget) : budget_(budget) {}
+
+Arena::~Arena() { release(); }
+
+void Arena::release() {
+  for (auto& c : chunks_) (void)hipFree(c.base);
+  chunks_.clear();
+  live_.clear();
+  held_ = 0;
+  used_ = 0;
+}
+
+void* Arena::alloc(size_t bytes) {
+  std::lock_guard<std::mutex> g(mu_);
+  bytes = (bytes + 255) & ~size_t(255);
+  if (bytes == 0) bytes = 256;
+  // best fit over free ranges
+  int best_c = -1;
+  size_t best_off = 0, best_sz = ~size_t(0);
+  for (size_t ci = 0; ci < chunks_.size(); ++ci)
+    for (auto& fr : chunks_[ci].free)
+      if (fr.second >= bytes && fr.second < best_sz) {
+        best_c = (int)ci;
+        best_off = fr.first;
+        best_sz = fr.second;
+      }
+  if (best_c < 0) {
+    size_t want = std::max(bytes, (size_t)(256ull << 20));
+    if (held_ + want > budget_) want = bytes;
+    if (held_ + want > budget_) return nullptr;
+    void* p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    Chunk c;
+    c.base = (char*)p;
+    c.size = want;
+    c.free[0] = want;
+    chunks_.push_back(c);
+    held_ += want;
+    best_c = (int)chunks_.size() - 1;
+    best_off = 0;
+    best_sz = want;
+  }
+  Chunk& c = chunks_[best_c];
+  c.free.erase(best_off);
+  if (best_sz > bytes) c.free[best_off + bytes] = best_sz - bytes;
+  char* p = c.base + best_off;
+  live_[p] = {best_c, bytes};
+  used_ += bytes;
+  high_ = std::max(high_, used_);
+  return p;
+}
+
+void Arena::give_back(int ci, size_t off, size_t sz) {
+  Chunk& c = chunks_[ci];
+  auto it = c.free.emplace(off, sz).first;
+  // merge with the next range
+  auto nx = std::next(it);
+  if (nx != c.free.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    c.free.erase(nx);
+  }
+  // merge with the previous range
+  if (it != c.free.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      c.free.erase(it);
+    }
+  }
+}
+
+void Arena::free(void* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> g(mu_);
+  auto it = live_.find((char*)p);
+  if (it == live_.end()) return;
+  int ci = it->second.first;
+  size_t sz = it->second.second;
+  size_t off = (char*)p - chunks_[ci].base;
+  live_.erase(it);
+  used_ -= sz;
+  give_back(ci, off, sz);
+}
+
+void Arena::shrink(void* p, size_t bytes) {
+  std::lock_guard<std::mutex> g(mu_);
+  auto it = live_.find((char*)p);
+  if (it == live_.end()) return;
+  bytes = (bytes + 255) & ~size_t(255);
+  if (bytes == 0) bytes = 256;
+  size_t old = it->second.second;
+  if (bytes >= old) return;
+  int ci = it->second.first;
+  size_t off = (char*)p - chunks_[ci].base;
+  it->second.second = bytes;
+  used_ -= old - bytes;
+  give_back(ci, off + bytes, old - bytes);
+}
+
+}  // namespace isr
+
+// ---------------------------------------------------------------------------
+// context and blob
+
+struct isr_blob {
+  isr_ctx* ctx = nullptr;
+  void* dev = nullptr;  // [voff area 256 B][bitmap][elem_ptr][values]
+  size_t dev_bytes = 0;
+  int order = 0, ncomp = 0, vbytes = 8, W = 0, precision = 0, status = 0;
+  int64_t n_elem = 0;
+  double tol = 0;
+  struct Hdr {
+    double U2, B, tau, dropped, err2, rel;
+    uint64_t kept, voff;
+  } comp[ISR_MAX_COMP];
+  uint64_t total_kept = 0;
+  u64* voff() const { return (u64*)dev; }
+  u64* bitmap() const { return (u64*)((char*)dev + 256); }
+  size_t bitmap_bytes() const { return (size_t)ncomp * n_elem * W * 8; }
+  u64* elem_ptr() const { return (u64*)((char*)bitmap() + bitmap_bytes()); }
+  size_t ptr_bytes() const { return (size_t)ncomp * (n_elem + 1) * 8; }
+  void* values() const { return (char*)elem_ptr() + ptr_bytes(); }
+  size_t values_bytes() const { return (size_t)total_kept * vbytes; }
+  static constexpr size_t HDR = 48, CHDR = 64;
+  size_t serialized() const { return HDR + CHDR * ncomp + bitmap_bytes() + ptr_bytes() + values_bytes(); }
+};
+
+struct isr_ctx {
+  int device = 0;
+  uint32_t flags = 0;
+  int num_cu = 256;
+  std::unique_ptr<isr::Arena> arena;
+  void* tables_dev = nullptr;
+  DevTables tab[ISR_MAX_ORDER + 1];
+  std::mutex mu;  // serialises device pipelines
+  std::unique_ptr<isr::Scheduler> sched;
+  int max_inflight = 8;
+  CompState* st_host = nullptr;  // pinned
+};
+
+static int set_device(isr_ctx* c) {
+  HIPCHK(hipSetDevice(c->device));
+  return ISR_OK;
+}
+
+static int upload_tables(isr_ctx* c) {
+  // one allocation: per order A, V, w3, g3 (FP64) then A32, V32 (FP32)
+  std::vector<char> host;
+  size_t offs[ISR_MAX_ORDER + 1][6];
+  for (int N = 1; N <= ISR_MAX_ORDER; ++N) {
+    HostTables t;
+    if (!host_tables(N, &t)) return fail(ISR_EINVAL, "table generation failed for order %d", N);
+    const int n = N + 1, n2 = n * n, n3 = n2 * n;
+    auto put = [&](const void* src, size_t bytes) {
+      size_t o = (host.size() + 255) & ~size_t(255);
+      host.resize(o + bytes);
+      std::memcpy(host.data() + o, src, bytes);
+      return o;
+    };
+    offs[N][0] = put(t.A, n2 * 8);
+    offs[N][1] = put(t.V, n2 * 8);
+    offs[N][2] = put(t.w3, n3 * 8);
+    offs[N][3] = put(t.g3, n3 * 8);
+    float a32[256], v32[256];
+    for (int k = 0; k < n2; ++k) {
+      a32[k] = (float)t.A[k];
+      v32[k] = (float)t.V[k];
+    }
+    offs[N][4] = put(a32, n2 * 4);
+    offs[N][5] = put(v32, n2 * 4);
+  }
+  HIPCHK(hipMalloc(&c->tables_dev, host.size()));
+  HIPCHK(hipMemcpy(c->tables_dev, host.data(), host.size(), hipMemcpyHostToDevice));
+  char* base = (char*)c->tables_dev;
+  for (int N = 1; N <= ISR_MAX_ORDER; ++N) {
+    c->tab[N].A = (const double*)(base + offs[N][0]);
+    c->tab[N].V = (const double*)(base + offs[N][1]);
+    c->tab[N].w3 = (const double*)(base + offs[N][2]);
+    c->tab[N].g3 = (const double*)(base + offs[N][3]);
+    c->tab[N].A32 = (const float*)(base + offs[N][4]);
+    c->tab[N].V32 = (const float*)(base + offs[N][5]);
+  }
+  return ISR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// argument checks and sizes
+
+static int check_field(const isr_field* f) {
+  if (!f) return fail(ISR_EINVAL, "field descriptor is NULL");
+  if (!f->field) return fail(ISR_EINVAL, "field pointer is NULL");
+  if (((uintptr_t)f->field) & 7) return fail(ISR_EINVAL, "field pointer is not 8-byte aligned");
+  if (f->elem_jac && (((uintptr_t)f->elem_jac) & 7)) return fail(ISR_EINVAL, "elem_jac is not 8-byte aligned");
+  if (f->order < 1 || f->order > ISR_MAX_ORDER) return fail(ISR_EINVAL, "order %d outside [1, %d]", f->order, ISR_MAX_ORDER);
+  if (f->ncomp < 1 || f->ncomp > ISR_MAX_COMP) return fail(ISR_EINVAL, "ncomp %d outside [1, %d]", f->ncomp, ISR_MAX_COMP);
+  if (f->n_elem < 1) return fail(ISR_EINVAL, "n_elem must be >= 1");
+  const long long n = f->order + 1, n3 = n * n * n;
+  if ((unsigned long long)f->n_elem * n3 >= (1ull << 32)) return fail(ISR_EINVAL, "n_elem * (order+1)^3 must be < 2^32");
+  if (std::isnan(f->tol)) return fail(ISR_EINVAL, "tol is NaN");
+  if (f->precision != ISR_PREC_FP64 && f->precision != ISR_PREC_FP32 && f->precision != ISR_PREC_BF16)
+    return fail(ISR_EINVAL, "unknown precision %d", f->precision);
+  if (f->comp_stride < 0 || (f->comp_stride > 0 && f->comp_stride < f->n_elem * n3))
+    return fail(ISR_EINVAL, "comp_stride smaller than one component");
+  return ISR_OK;
+}
+
+namespace isr {
+
+Sizes plan_sizes(const isr_field* f) {
+  Sizes z;
+  const long long n = f->order + 1, n3 = n * n * n;
+  const int nc = f->ncomp;
+  z.nv = (u64)f->n_elem * n3;
+  z.W = words_per_elem(f->order);
+  z.tiles = tiles_per_comp(f->order, f->n_elem);
+  z.vbytes = f->precision == ISR_PREC_FP64 ? 8 : 4;
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    size_t r = o;
+    o += (b + 255) & ~size_t(255);
+    return r;
+  };
+  z.off_histE = take((size_t)nc * HBINS * sizeof(HistBin));
+  z.off_histN = take((size_t)nc * HBINS * sizeof(HistBin));
+  z.off_histR = take((size_t)nc * HBINS * sizeof(HistBin));
+  z.off_histL = take((size_t)(NLEV - 1) * nc * RBINS * sizeof(HistBin));
+  z.off_st = take((size_t)nc * sizeof(CompState));
+  z.off_ticket = take(256);
+  z.off_lookback = take((size_t)nc * z.tiles * 8);
+  z.zero_bytes = o;
+  z.list_cap = z.nv;
+  z.off_lists = take((size_t)nc * 2 * z.list_cap * 8);
+  z.scratch_bytes = o;
+  z.blob_max = 256 + (size_t)nc * f->n_elem * z.W * 8 + (size_t)nc * (f->n_elem + 1) * 8 + (size_t)nc * z.nv * z.vbytes;
+  return z;
+}
+
+}  // namespace isr
+
+static Job make_job(isr_ctx* c, const isr_field* f, const Sizes& z, char* scratch, isr_blob* b) {
+  Job j;
+  std::memset(&j, 0, sizeof(j));
+  const long long n = f->order + 1, n3 = n * n * n;
+  j.u = f->field;
+  j.jac = f->elem_jac;
+  j.comp_stride = f->comp_stride ? f->comp_stride : f->n_elem * n3;
+  j.n_elem = f->n_elem;
+  j.order = f->order;
+  j.ncomp = f->ncomp;
+  j.precision = f->precision;
+  j.vbytes = z.vbytes;
+  j.tol = f->tol;
+  for (int k = 0; k < 8; ++k) j.Bov[k] = -1.0;
+  j.tab = c->tab[f->order];
+  j.histE = (HistBin*)(scratch + z.off_histE);
+  j.histN = (HistBin*)(scratch + z.off_histN);
+  j.histR = (HistBin*)(scratch + z.off_histR);
+  j.histL = (HistBin*)(scratch + z.off_histL);
+  j.st = (CompState*)(scratch + z.off_st);
+  j.ticket = (u32*)(scratch + z.off_ticket);
+  j.lookback = (u64*)(scratch + z.off_lookback);
+  j.lists = (u64*)(scratch + z.off_lists);
+  j.list_cap = z.list_cap;
+  j.bitmap = b->bitmap();
+  j.elem_ptr = b->elem_ptr();
+  j.values = b->values();
+  j.voff = b->voff();
+  return j;
+}
+
+// Enqueue every phase of one compression on stream s (no host sync).
+namespace isr {
+
+int enqueue_pipeline(isr_ctx* c, const Job& j, const Sizes& z, hipStream_t s, hipEvent_t* ev) {
+  const int nc = j.ncomp;
+  const long long tiles = z.tiles;
+  const int target = c->num_cu * 4;
+  int gx = (int)std::min<long long>(tiles, std::max(1, target / nc));
+  const int nn = j.order + 1, tile_vals = (256 / (nn * nn) > 0 ? 256 / (nn * nn) : 1) * nn * nn * nn;
+  // each workgroup may add at most 2^21 - 1 values to one LDS bin
+  const long long min_gx = (tiles * (long long)tile_vals + (1ll << 21) - 2) / ((1ll << 21) - 1);
+  gx = (int)std::max<long long>(gx, std::min<long long>(tiles, min_gx));
+  auto rec = [&](int k) {
+    if (ev) (void)hipEventRecord(ev[k], s);
+  };
+  HIPCHK(launch_zero((void*)j.histE, z.zero_bytes, s));
+  rec(0);
+  HIPCHK(launch_pass1(j, gx, s));
+  rec(1);
+  HIPCHK(launch_select1(j, s));
+  rec(2);
+  HIPCHK(launch_pass2(j, gx, s));
+  rec(3);
+  const int rgx = std::max(1, std::min(256, (int)((z.nv / 4096) + 1)));
+  HIPCHK(launch_refine(j, 2, rgx, s));
+  HIPCHK(launch_select(j, 2, s));
+  for (int L = 3; L <= NLEV; ++L) {
+    HIPCHK(launch_refine(j, L, rgx, s));
+    HIPCHK(launch_select(j, L, s));
+  }
+  rec(4);
+  const int g3 = (int)std::min<long long>(tiles * nc, (long long)c->num_cu * 4);
+  HIPCHK(launch_pass3(j, g3, s));
+  rec(5);
+  HIPCHK(launch_finalize(j, s));
+  rec(6);
+  return ISR_OK;
+}
+
+}  // namespace isr
+
+static int status_from_flags(int flags) {
+  if (flags & ST_NONFINITE) return fail(ISR_EINVAL, "field holds a non-finite value");
+  if (flags & ST_OVERFLOW) return fail(ISR_EINVAL, "an energy overflowed FP64 (field magnitude too large)");
+  if (flags & (ST_SPIN | ST_LIST)) return fail(ISR_EDEVICE, "internal selection error (flags 0x%x)", flags);
+  return ISR_OK;
+}
+
+static isr_blob* new_blob(isr_ctx* c, const isr_field* f, const Sizes& z) {
+  isr_blob* b = new isr_blob();
+  b->ctx = c;
+  b->order = f->order;
+  b->ncomp = f->ncomp;
+  b->n_elem = f->n_elem;
+  b->vbytes = z.vbytes;
+  b->W = z.W;
+  b->tol = f->tol;
+  b->precision = f->precision;
+  b->dev_bytes = z.blob_max;
+  b->dev = c->arena->alloc(z.blob_max);
+  if (!b->dev) {
+    delete b;
+    return nullptr;
+  }
+  return b;
+}
+
+static void fill_stats(isr_blob* b, const CompState* hs, isr_stats* st) {
+  for (int k = 0; k < b->ncomp; ++k) {
+    auto& h = b->comp[k];
+    h.U2 = hs[k].U2;
+    h.B = hs[k].B;
+    h.tau = hs[k].tau;
+    h.dropped = hs[k].dropped;
+    h.err2 = hs[k].err2;
+    h.rel = hs[k].rel;
+    h.kept = hs[k].kept;
+  }
+  uint64_t vo = 0;
+  for (int k = 0; k < b->ncomp; ++k) {
+    b->comp[k].voff = vo;
+    vo += b->comp[k].kept;
+  }
+  b->total_kept = vo;
+  if (st) {
+    for (int k = 0; k < b->ncomp; ++k) {
+      st->norm2[k] = b->comp[k].U2;
+      st->budget[k] = b->comp[k].B;
+      st->tau[k] = b->comp[k].tau;
+      st->dropped[k] = b->comp[k].dropped;
+      st->err2[k] = b->comp[k].err2;
+      st->rel_err[k] = b->comp[k].rel;
+      st->kept[k] = b->comp[k].kept;
+    }
+    const long long n = b->order + 1;
+    st->in_bytes = (uint64_t)b->ncomp * b->n_elem * n * n * n * 8;
+    st->blob_bytes = b->serialized();
+    st->cr = st->in_bytes ? (double)((int64_t)st->in_bytes - (int64_t)st->blob_bytes) / (double)st->in_bytes : 0.0;
+    st->precision = b->precision;
+  }
+}
+
+namespace isr {
+
+// Run one compression to completion on stream s (caller holds ctx->mu).
+int run_compress(isr_ctx* c, const isr_field* f, isr_blob** out, isr_stats* st) {
+  *out = nullptr;
+  int rc = check_field(f);
+  if (rc) return rc;
+  if (f->precision != ISR_PREC_FP64) {
+    rc = mixed_supported(f->order);
+    if (rc) return fail(ISR_EINVAL, "precision %d is not available for order %d", f->precision, f->order);
+  }
+  const double t_start = now_s();
+  Sizes z = plan_sizes(f);
+  hipStream_t s = (hipStream_t)f->stream;
+  char* scratch = (char*)c->arena->alloc(z.scratch_bytes);
+  if (!scratch) return fail(ISR_ENOMEM, "scratch of %zu bytes does not fit the HBM budget", z.scratch_bytes);
+  isr_blob* b = new_blob(c, f, z);
+  if (!b) {
+    c->arena->free(scratch);
+    return fail(ISR_ENOMEM, "blob of %zu bytes does not fit the HBM budget", z.blob_max);
+  }
+  Job j = make_job(c, f, z, scratch, b);
+  const bool timing = (c->flags & ISR_FLAG_TIMING) && st;
+  hipEvent_t ev[7] = {};
+  if (timing)
+    for (auto& e : ev) (void)hipEventCreate(&e);
+  CompState* hs = c->st_host;
+  int iters = 0;
+  float repair_ms = 0.f;
+  for (;;) {
+    rc = enqueue_pipeline(c, j, z, s, timing ? ev : nullptr);
+    if (rc) break;
+    if (hipMemcpyAsync(hs, j.st, sizeof(CompState) * f->ncomp, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      rc = fail(ISR_EDEVICE, "device pipeline failed: %s", hipGetErrorString(hipGetLastError()));
+      break;
+    }
+    int flags = 0;
+    for (int k = 0; k < f->ncomp; ++k) flags |= hs[k].flags;
+    rc = status_from_flags(flags);
+    if (rc) break;
+    if (timing) {
+      float ms[6];
+      for (int k = 0; k < 6; ++k) (void)hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]);
+      if (iters == 0) {
+        st->phase_ms[0] = ms[0];
+        st->phase_ms[1] = ms[1];
+        st->phase_ms[2] = ms[2];
+        st->phase_ms[3] = ms[3];
+        st->phase_ms[4] = ms[4];
+        st->phase_ms[5] = ms[5];
+      } else {
+        for (int k = 0; k < 6; ++k) repair_ms += ms[k];
+      }
+    }
+    // rounding repair: lower B where the measured error exceeds tol
+    bool again = false;
+    if (f->tol >= 0.0 && iters < 4) {
+      for (int k = 0; k < f->ncomp; ++k) {
+        if (hs[k].rel > f->tol) {
+          const double fr = f->tol / hs[k].rel;
+          j.Bov[k] = (hs[k].B * (fr * fr)) * (1.0 - 0x1p-20);
+          again = true;
+        } else {
+          j.Bov[k] = hs[k].B;  // unchanged, reproduces the same result
+        }
+      }
+    }
+    if (!again) break;
+    ++iters;
+  }
+  if (timing) {
+    st->phase_ms[6] = repair_ms;
+    for (auto& e : ev) (void)hipEventDestroy(e);
+  }
+  c->arena->free(scratch);
+  if (rc) {
+    c->arena->free(b->dev);
+    delete b;
+    return rc;
+  }
+  fill_stats(b, hs, st);
+  bool within = true;
+  if (f->tol >= 0.0)
+    for (int k = 0; k < f->ncomp; ++k) within = within && !(hs[k].rel > f->tol);
+  b->status = within ? ISR_OK : ISR_ETOL;
+  // return the unused tail of the worst-case value reservation
+  const size_t used = 256 + b->bitmap_bytes() + b->ptr_bytes() + b->values_bytes();
+  c->arena->shrink(b->dev, used);
+  b->dev_bytes = (used + 255) & ~size_t(255);
+  if (st) {
+    st->repair_iters = iters;
+    st->status = b->status;
+    st->t_start = t_start;
+    st->t_done = now_s();
+  }
+  *out = b;
+  if (!within) fail(ISR_ETOL, "relative error above tol after %d repairs", iters);
+  return b->status;
+}
+
+}  // namespace isr
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+const char* isr_version(void) { return "isr 0.1 (gfx950)"; }
+
+const char* isr_last_error(void) { return g_err.c_str(); }
+
+int isr_create(const isr_config* cfg, isr_ctx** out) {
+  if (!out) return fail(ISR_EINVAL, "out is NULL");
+  *out = nullptr;
+  isr_config d;
+  std::memset(&d, 0, sizeof(d));
+  if (cfg) d = *cfg;
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (d.device < 0 || d.device >= ndev) return fail(ISR_EINVAL, "device %d not present (%d devices)", d.device, ndev);
+  std::unique_ptr<isr_ctx> c(new isr_ctx());
+  c->device = d.device;
+  c->flags = d.flags;
+  c->max_inflight = d.max_inflight > 0 ? d.max_inflight : 8;
+  HIPCHK(hipSetDevice(c->device));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, c->device));
+  c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  c->arena.reset(new isr::Arena(d.hbm_budget_bytes ? d.hbm_budget_bytes : (64ull << 30)));
+  int rc = upload_tables(c.get());
+  if (rc) return rc;
+  HIPCHK(hipHostMalloc((void**)&c->st_host, sizeof(CompState) * ISR_MAX_COMP * 64, hipHostMallocDefault));
+  c->sched.reset(new isr::Scheduler(c.get()));
+  *out = c.release();
+  return ISR_OK;
+}
+
+int isr_destroy(isr_ctx* c) {
+  if (!c) return fail(ISR_EINVAL, "ctx is NULL");
+  (void)hipSetDevice(c->device);
+  c->sched.reset();
+  (void)hipDeviceSynchronize();
+  c->arena.reset();
+  if (c->tables_dev) (void)hipFree(c->tables_dev);
+  if (c->st_host) (void)hipHostFree(c->st_host);
+  delete c;
+  return ISR_OK;
+}
+
+int isr_compress(isr_ctx* c, const isr_field* f, isr_blob** out, isr_stats* st) {
+  if (!c || !out) return fail(ISR_EINVAL, "ctx or out is NULL");
+  *out = nullptr;
+  if (st) std::memset(st, 0, sizeof(*st));
+  int rc = set_device(c);
+  if (rc) return rc;
+  const double t0 = now_s();
+  std::lock_guard<std::mutex> g(c->mu);
+  rc = run_compress(c, f, out, st);
+  if (st) st->t_submit = t0;
+  return rc;
+}
+
+int isr_compress_batch(isr_ctx* c, const isr_field* fs, int32_t count, isr_blob** outs, isr_stats* st) {
+  if (!c || !fs || !outs || count < 0) return fail(ISR_EINVAL, "bad batch arguments");
+  int rc = set_device(c);
+  if (rc) return rc;
+  for (int i = 0; i < count; ++i) {
+    outs[i] = nullptr;
+    int r = check_field(&fs[i]);
+    if (r) return r;
+  }
+  std::lock_guard<std::mutex> g(c->mu);
+  return isr::run_batch(c, fs, count, outs, st);
+}
+
+int isr_submit(isr_ctx* c, const isr_field* f, uint64_t* req) {
+  if (!c || !req) return fail(ISR_EINVAL, "ctx or req is NULL");
+  int rc = check_field(f);
+  if (rc) return rc;
+  rc = set_device(c);
+  if (rc) return rc;
+  return c->sched->submit(f, req);
+}
+
+int isr_poll(isr_ctx* c, uint64_t req, int32_t wait_ms, isr_blob** out, isr_stats* st) {
+  if (!c) return fail(ISR_EINVAL, "ctx is NULL");
+  if (out) *out = nullptr;
+  return c->sched->poll(req, wait_ms, out, st);
+}
+
+int isr_decompress(isr_ctx* c, const isr_blob* b, void* d_out, int32_t out_prec, void* stream) {
+  if (!c || !b || !d_out) return fail(ISR_EINVAL, "ctx, blob or output is NULL");
+  if (out_prec != ISR_PREC_FP64 && out_prec != ISR_PREC_FP32) return fail(ISR_EINVAL, "out_prec must be FP64 or FP32");
+  if (((uintptr_t)d_out) & 7) return fail(ISR_EINVAL, "output pointer is not 8-byte aligned");
+  int rc = set_device(c);
+  if (rc) return rc;
+  Job j;
+  std::memset(&j, 0, sizeof(j));
+  j.n_elem = b->n_elem;
+  j.order = b->order;
+  j.ncomp = b->ncomp;
+  j.vbytes = b->vbytes;
+  j.tab = c->tab[b->order];
+  j.bitmap = b->bitmap();
+  j.elem_ptr = b->elem_ptr();
+  j.values = b->values();
+  j.voff = b->voff();
+  const long long total = (long long)tiles_per_comp(b->order, b->n_elem) * b->ncomp;
+  const int grid = (int)std::min<long long>(total, (long long)c->num_cu * 8);
+  HIPCHK(launch_decompress(j, d_out, out_prec == ISR_PREC_FP64, grid, (hipStream_t)stream));
+  return ISR_OK;
+}
+
+int isr_forward(isr_ctx* c, const isr_field* f, void* d_coef) {
+  if (!c || !d_coef) return fail(ISR_EINVAL, "ctx or output is NULL");
+  int rc = check_field(f);
+  if (rc) return rc;
+  rc = set_device(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> g(c->mu);
+  Job j;
+  std::memset(&j, 0, sizeof(j));
+  const long long n = f->order + 1, n3 = n * n * n;
+  j.u = f->field;
+  j.comp_stride = f->comp_stride ? f->comp_stride : f->n_elem * n3;
+  j.n_elem = f->n_elem;
+  j.order = f->order;
+  j.ncomp = f->ncomp;
+  j.precision = f->precision;
+  j.tab = c->tab[f->order];
+  const long long total = (long long)tiles_per_comp(f->order, f->n_elem) * f->ncomp;
+  const int grid = (int)std::min<long long>(total, (long long)c->num_cu * 8);
+  hipStream_t s = (hipStream_t)f->stream;
+  if (f->precision == ISR_PREC_FP64) {
+    HIPCHK(launch_forward(j, d_coef, grid, s));
+  } else {
+    HIPCHK(launch_forward_mixed(j, d_coef, grid, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return ISR_OK;
+}
+
+int isr_blob_info(const isr_blob* b, int32_t* order, int32_t* ncomp, int64_t* n_elem, int32_t* value_bytes) {
+  if (!b) return fail(ISR_EINVAL, "blob is NULL");
+  if (order) *order = b->order;
+  if (ncomp) *ncomp = b->ncomp;
+  if (n_elem) *n_elem = b->n_elem;
+  if (value_bytes) *value_bytes = b->vbytes;
+  return ISR_OK;
+}
+
+int isr_blob_size(const isr_blob* b, uint64_t* bytes) {
+  if (!b || !bytes) return fail(ISR_EINVAL, "blob or bytes is NULL");
+  *bytes = b->serialized();
+  return ISR_OK;
+}
+
+static void put_hdr(const isr_blob* b, char* p) {
+  std::memcpy(p, "ISR1", 4);
+  uint32_t ver = 1;
+  std::memcpy(p + 4, &ver, 4);
+  int32_t v32 = b->order;
+  std::memcpy(p + 8, &v32, 4);
+  v32 = b->ncomp;
+  std::memcpy(p + 12, &v32, 4);
+  int64_t ne = b->n_elem;
+  std::memcpy(p + 16, &ne, 8);
+  v32 = b->vbytes;
+  std::memcpy(p + 24, &v32, 4);
+  v32 = b->W;
+  std::memcpy(p + 28, &v32, 4);
+  std::memcpy(p + 32, &b->tol, 8);
+  v32 = b->precision;
+  std::memcpy(p + 40, &v32, 4);
+  v32 = b->status;
+  std::memcpy(p + 44, &v32, 4);
+  for (int k = 0; k < b->ncomp; ++k) std::memcpy(p + isr_blob::HDR + isr_blob::CHDR * k, &b->comp[k], isr_blob::CHDR);
+}
+
+int isr_blob_to_host(const isr_blob* b, void* buf, uint64_t cap) {
+  if (!b || !buf) return fail(ISR_EINVAL, "blob or buffer is NULL");
+  const size_t need = b->serialized();
+  if (cap < need) return fail(ISR_EINVAL, "buffer of %llu bytes is smaller than the blob (%zu)", (unsigned long long)cap, need);
+  int rc = set_device(b->ctx);
+  if (rc) return rc;
+  char* p = (char*)buf;
+  put_hdr(b, p);
+  const size_t hb = isr_blob::HDR + isr_blob::CHDR * b->ncomp;
+  const size_t body = b->bitmap_bytes() + b->ptr_bytes() + b->values_bytes();
+  HIPCHK(hipMemcpy(p + hb, b->bitmap(), body, hipMemcpyDeviceToHost));
+  return ISR_OK;
+}
+
+int isr_blob_from_host(isr_ctx* c, const void* buf, uint64_t nbytes, isr_blob** out) {
+  if (!c || !buf || !out) return fail(ISR_EINVAL, "ctx, buffer or out is NULL");
+  *out = nullptr;
+  const char* p = (const char*)buf;
+  if (nbytes < isr_blob::HDR || std::memcmp(p, "ISR1", 4) != 0) return fail(ISR_EINVAL, "not an ISR1 blob");
+  std::unique_ptr<isr_blob> b(new isr_blob());
+  int32_t v32;
+  int64_t ne;
+  std::memcpy(&v32, p + 8, 4);
+  b->order = v32;
+  std::memcpy(&v32, p + 12, 4);
+  b->ncomp = v32;
+  std::memcpy(&ne, p + 16, 8);
+  b->n_elem = ne;
+  std::memcpy(&v32, p + 24, 4);
+  b->vbytes = v32;
+  std::memcpy(&v32, p + 28, 4);
+  b->W = v32;
+  std::memcpy(&b->tol, p + 32, 8);
+  std::memcpy(&v32, p + 40, 4);
+  b->precision = v32;
+  std::memcpy(&v32, p + 44, 4);
+  b->status = v32;
+  if (b->order < 1 || b->order > ISR_MAX_ORDER || b->ncomp < 1 || b->ncomp > ISR_MAX_COMP || b->n_elem < 1 ||
+      (b->vbytes != 4 && b->vbytes != 8) || b->W != words_per_elem(b->order))
+    return fail(ISR_EINVAL, "corrupt blob header");
+  if (nbytes < isr_blob::HDR + isr_blob::CHDR * (size_t)b->ncomp) return fail(ISR_EINVAL, "truncated blob");
+  uint64_t tk = 0;
+  for (int k = 0; k < b->ncomp; ++k) {
+    std::memcpy(&b->comp[k], p + isr_blob::HDR + isr_blob::CHDR * k, isr_blob::CHDR);
+    if (b->comp[k].voff != tk) return fail(ISR_EINVAL, "corrupt blob component offsets");
+    tk += b->comp[k].kept;
+  }
+  b->total_kept = tk;
+  if (nbytes != b->serialized()) return fail(ISR_EINVAL, "blob size %llu does not match its header (%zu)", (unsigned long long)nbytes, b->serialized());
+  // the offset tables must agree with the bitmaps and the kept counts, since
+  // decompression indexes the values with them
+  {
+    const size_t hb0 = isr_blob::HDR + isr_blob::CHDR * b->ncomp;
+    const u64* bm = (const u64*)(p + hb0);
+    const u64* ep = (const u64*)(p + hb0 + b->bitmap_bytes());
+    for (int k = 0; k < b->ncomp; ++k) {
+      const u64* e = ep + (size_t)k * (b->n_elem + 1);
+      const u64* m = bm + (size_t)k * b->n_elem * b->W;
+      if (e[0] != 0 || e[b->n_elem] != b->comp[k].kept) return fail(ISR_EINVAL, "corrupt blob offset table");
+      for (int64_t q = 0; q < b->n_elem; ++q) {
+        u64 pc = 0;
+        for (int w = 0; w < b->W; ++w) pc += (u64)__builtin_popcountll(m[q * b->W + w]);
+        if (e[q + 1] < e[q] || e[q + 1] - e[q] != pc) return fail(ISR_EINVAL, "corrupt blob bitmap or offsets");
+      }
+    }
+  }
+  int rc = set_device(c);
+  if (rc) return rc;
+  b->ctx = c;
+  b->dev_bytes = 256 + b->bitmap_bytes() + b->ptr_bytes() + b->values_bytes();
+  b->dev = c->arena->alloc(b->dev_bytes);
+  if (!b->dev) return fail(ISR_ENOMEM, "blob does not fit the HBM budget");
+  u64 vo[ISR_MAX_COMP];
+  for (int k = 0; k < b->ncomp; ++k) vo[k] = b->comp[k].voff;
+  const size_t hb = isr_blob::HDR + isr_blob::CHDR * b->ncomp;
+  if (hipMemcpy(b->voff(), vo, 8 * b->ncomp, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->bitmap(), p + hb, nbytes - hb, hipMemcpyHostToDevice) != hipSuccess) {
+    c->arena->free(b->dev);
+    return fail(ISR_EDEVICE, "blob upload failed");
+  }
+  *out = b.release();
+  return ISR_OK;
+}
+
+void isr_blob_free(isr_blob* b) {
+  if (!b) return;
+  if (b->ctx && b->dev) {
+    (void)hipSetDevice(b->ctx->device);
+    b->ctx->arena->free(b->dev);
+  }
+  delete b;
+}
+
+int isr_gll_tables(int32_t order, double* xi, double* w, double* V, double* A, double* gamma, double* w3,
+                   double* g3) {
+  HostTables t;
+  if (!host_tables(order, &t)) return fail(ISR_EINVAL, "order %d outside [1, %d]", order, ISR_MAX_ORDER);
+  const int n = order + 1, n2 = n * n, n3 = n2 * n;
+  if (xi) std::memcpy(xi, t.xi, n * 8);
+  if (w) std::memcpy(w, t.w, n * 8);
+  if (gamma) std::memcpy(gamma, t.gamma, n * 8);
+  if (V) std::memcpy(V, t.V, n2 * 8);
+  if (A) std::memcpy(A, t.A, n2 * 8);
+  if (w3) std::memcpy(w3, t.w3, n3 * 8);
+  if (g3) std::memcpy(g3, t.g3, n3 * 8);
+  return ISR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Host-side runtime pieces: arena, sizes, pipeline entry points, scheduler.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <utility>
+#include <vector>
+
+#include "isr.h"
+#include "isr_internal.h"
+
+namespace isr {
+
+// Device sub-allocator: large hipMalloc chunks, best-fit ranges, coalescing,
+// in-place shrink; never holds more than `budget` bytes of chunks.
+class Arena {
+ public:
+  explicit Arena(uint64_t budget);
+  ~Arena();
+  void* alloc(size_t bytes);  // nullptr when the budget or the device is exhausted
+  void free(void* p);
+  void shrink(void* p, size_t bytes);
+  void release();
+  uint64_t budget() const { return budget_; }
+  uint64_t used() const { return used_; }
+  uint64_t high_water() const { return high_; }
+
+ private:
+  struct Chunk {
+    char* base;
+    size_t size;
+    std::map<size_t, size_t> free;  // offset -> length
+  };
+  void give_back(int ci, size_t off, size_t sz);
+  std::mutex mu_;
+  uint64_t budget_, held_ = 0, used_ = 0, high_ = 0;
+  std::vector<Chunk> chunks_;
+  std::map<char*, std::pair<int, size_t>> live_;
+};
+
+// Sizes and scratch layout of one compression.
+struct Sizes {
+  u64 nv = 0;        // values per component
+  int W = 0;         // bitmap words per element
+  long long tiles = 0;
+  int vbytes = 8;
+  size_t off_histE = 0, off_histN = 0, off_histR = 0, off_histL = 0, off_st = 0, off_ticket = 0,
+         off_lookback = 0, off_lists = 0;
+  size_t zero_bytes = 0;     // leading scratch bytes to clear
+  u64 list_cap = 0;
+  size_t scratch_bytes = 0;
+  size_t blob_max = 0;       // worst-case blob allocation
+};
+Sizes plan_sizes(const isr_field* f);
+
+int enqueue_pipeline(isr_ctx* c, const Job& j, const Sizes& z, hipStream_t s, hipEvent_t* ev);
+int run_compress(isr_ctx* c, const isr_field* f, isr_blob** out, isr_stats* st);
+int run_batch(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_stats* st);
+int mixed_supported(int order);
+hipError_t launch_forward_mixed(const Job& j, void* coef, int grid, hipStream_t s);
+
+// Request queue behind isr_submit / isr_poll.
+class Scheduler {
+ public:
+  explicit Scheduler(isr_ctx* c);
+  ~Scheduler();
+  int submit(const isr_field* f, uint64_t* req);
+  int poll(uint64_t req, int wait_ms, isr_blob** out, isr_stats* st);
+
+ private:
+  struct Req {
+    uint64_t id;
+    isr_field f;
+    double t_submit;
+    bool done = false;
+    int status = 0;
+    isr_blob* blob = nullptr;
+    isr_stats st;
+  };
+  void loop();
+  isr_ctx* ctx_;
+  std::mutex mu_;
+  std::condition_variable cv_, done_cv_;
+  std::deque<uint64_t> queue_;
+  std::map<uint64_t, Req> reqs_;
+  uint64_t next_id_ = 1;
+  bool stop_ = false;
+  std::thread worker_;
+};
+
+}  // namespace isr
