@@ -158,19 +158,20 @@ DEV u64 hist_total(const HistBin* H) {
 }
 
 // ---- LDS histogram window of one workgroup ----------------------------------
+// HC copies of every bin (lane parity picks the copy) halve same-address
+// atomic conflicts inside a wave.
+constexpr int HC = 2;
 struct LdsHist {
-  u64 w[WIN][2];  // [0] = (count << 43) + sum(sig & (2^21-1)), [1] = sum(sig >> 21)
-  u32 zero;       // exact zeros
-  int lo;         // exponent of w[0]
+  u64 w[WIN][HC][2];  // [0] = (count << 43) + sum(sig & (2^21-1)), [1] = sum(sig >> 21)
+  u32 zero;           // exact zeros
+  int lo;             // exponent of w[0]
   int maxE;
   int pad;
 };
 
 DEV void lh_init(LdsHist& h, int tid, int nthr) {
-  for (int b = tid; b < WIN; b += nthr) {
-    h.w[b][0] = 0ull;
-    h.w[b][1] = 0ull;
-  }
+  u64* p = &h.w[0][0][0];
+  for (int k = tid; k < WIN * HC * 2; k += nthr) p[k] = 0ull;
   if (tid == 0) {
     h.zero = 0u;
     h.maxE = 0;
@@ -199,8 +200,9 @@ DEV void lh_insert(LdsHist& h, HistBin* g, double v) {
   if (E == 2047) sig = 0;
   int b = E - h.lo;
   if ((unsigned)b < (unsigned)WIN) {
-    atomicAdd(&h.w[b][0], (1ull << 43) + (sig & M21));
-    atomicAdd(&h.w[b][1], sig >> 21);
+    const int cp = lane_id() & (HC - 1);
+    atomicAdd(&h.w[b][cp][0], (1ull << 43) + (sig & M21));
+    atomicAdd(&h.w[b][cp][1], sig >> 21);
   } else {
     global_bin_add(g, E, 1ull, sig & M21, sig >> 21);
   }
@@ -215,13 +217,95 @@ DEV void lh_place(LdsHist& h) { h.lo = h.maxE + WIN_HEAD - WIN + 1; }
 
 DEV void lh_flush(LdsHist& h, HistBin* g, int tid, int nthr) {
   for (int b = tid; b < WIN; b += nthr) {
-    u64 w0 = h.w[b][0], w1 = h.w[b][1];
-    if (w0 | w1) {
-      int E = h.lo + b;
-      global_bin_add(g, E, w0 >> 43, w0 & M43, w1);
+    u64 cnt = 0, lo = 0, hi = 0;
+    for (int cp = 0; cp < HC; ++cp) {
+      const u64 w0 = h.w[b][cp][0];
+      cnt += w0 >> 43;
+      lo += w0 & M43;
+      hi += h.w[b][cp][1];
     }
+    if (cnt | lo | hi) global_bin_add(g, h.lo + b, cnt, lo, hi);
   }
   if (tid == 0 && h.zero) atomicAdd(&g[0].cnt, (u64)h.zero);
+}
+
+// ---- candidate lists -------------------------------------------------------------
+// Wave-aggregated append; the counter may run past cap (then ST_LIST is set
+// and readers clamp to cap).
+DEV void list_append(u64* list, u64* count, u64 cap, bool m, u64 key, int* flag) {
+  const u64 bal = ballot(m);
+  if (bal == 0ull) return;
+  const int leader = __ffsll((long long)bal) - 1;
+  u64 base = 0;
+  if (lane_id() == leader) base = atomicAdd(count, (u64)__popcll(bal));
+  base = shfl64(base, leader);
+  if (m) {
+    const u64 pos = base + (u64)__popcll(bal & ((1ull << lane_id()) - 1ull));
+    if (pos < cap)
+      list[pos] = key;
+    else
+      atomicOr(flag, ST_LIST);
+  }
+}
+
+// ---- decoupled look-back --------------------------------------------------------
+// Descriptor per tile: flag << 62 | value; flag 1 = aggregate, 2 = inclusive
+// prefix.  publish() posts the tile's aggregate (tile 0 posts its prefix);
+// wait() reads 64 predecessors at a time (lane i: tile base - i) until one
+// carries an inclusive prefix, then posts the tile's own prefix.  Both run on
+// one whole wave.
+DEV u64 lb_load(const u64* p) { return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT); }
+DEV void lb_store(u64* p, u64 v) { __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT); }
+
+DEV u64 tile_agg(const u32* cntl, int ne) {
+  u64 agg = 0;
+  for (int k = 0; k < ne; ++k) agg += cntl[k];
+  return agg;
+}
+
+DEV void lookback_publish(u64* lb, long long t, const u32* cntl, int ne, u64* excl_out) {
+  if (lane_id() != 0) return;
+  const u64 agg = tile_agg(cntl, ne);
+  if (t == 0) {
+    lb_store(&lb[0], (2ull << 62) | agg);
+    *excl_out = 0ull;
+  } else {
+    lb_store(&lb[t], (1ull << 62) | agg);
+  }
+}
+
+constexpr int SPIN_LIMIT = 1 << 24;
+
+DEV void lookback_wait(u64* lb, long long t, const u32* cntl, int ne, int* flags, u64* excl_out) {
+  if (t == 0) return;
+  const int lane = lane_id();
+  u64 ex = 0;
+  long long base = t - 1;
+  for (;;) {
+    const long long idx = base - lane;
+    u64 sv = 2ull << 62;  // before tile 0: an inclusive prefix of 0
+    if (idx >= 0) {
+      int spins = 0;
+      for (;;) {
+        sv = lb_load(&lb[idx]);
+        if ((sv >> 62) != 0ull || ++spins >= SPIN_LIMIT) break;
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    if (ballot((sv >> 62) == 0ull)) {  // a predecessor never published (cannot happen)
+      if (lane == 0) atomicOr(flags, ST_SPIN);
+      break;
+    }
+    const u64 pm = ballot((sv >> 62) == 2ull);
+    const int stop = pm ? (__ffsll((long long)pm) - 1) : 63;
+    ex += wave_sum64(lane <= stop ? (sv & M62) : 0ull);
+    if (pm) break;
+    base -= 64;
+  }
+  if (lane == 0) {
+    lb_store(&lb[t], (2ull << 62) | (ex + tile_agg(cntl, ne)));
+    *excl_out = ex;
+  }
 }
 
 // ---- FP64 fixed-order contraction ---------------------------------------------
@@ -250,7 +334,5 @@ DEV void load_tile(double* __restrict__ dst, const double* __restrict__ src, int
   }
 }
 
-// Bounded spin for cross-workgroup flags (never unbounded on the device).
-constexpr int SPIN_LIMIT = 1 << 24;
 
 }  // namespace isr

@@ -58,7 +58,10 @@ struct alignas(256) CompState {
   int32_t level;      // last level decided
   int32_t resolved;   // tau final
   int32_t flags;      // ST_* below
-  int32_t repair;     // host: B was overridden
+  int32_t win_lo;     // exponent bins [win_lo, win_hi) captured speculatively
+  int32_t win_hi;     //   by pass 1 (empty when win_lo >= win_hi)
+  int32_t need_pass2; // boundary bin outside the window: run the candidate pass
+  int32_t list0_exact;  // list 0 holds exactly the boundary bin's energies
   int32_t pad[3];
 };
 
@@ -96,6 +99,9 @@ struct Job {
   HistBin* histN;      // [ncomp][HBINS]  norm terms
   HistBin* histR;      // [ncomp][HBINS]  error terms
   HistBin* histL;      // [NLEV-1][ncomp][RBINS]  refinement levels 2..6
+  HistBin* histEs;     // [ncomp][HBINS]  energies of the sampled tiles
+  HistBin* histNs;     // [ncomp][HBINS]  norm terms of the sampled tiles
+  long long sample_stride;  // every sample_stride-th tile is sampled; 0 = no sample pass
   CompState* st;       // [ncomp]
   u64* lists;          // [ncomp][2][list_cap]
   u64 list_cap;
@@ -108,19 +114,27 @@ struct Job {
   u64* voff;           // [ncomp] offset of each component's first value
 };
 
-// Host launchers (kernels are in isr_kernels.hip).
+// Streaming passes (isr_passes.cuh), one instantiation file per precision.
+enum PassKind { K_PASS1 = 0, K_PASS2 = 1, K_PASS3 = 2, K_DECOMP = 3, K_FORWARD = 4 };
 int tiles_per_comp(int order, long long n_elem);
 int words_per_elem(int order);
+// grid: x extent (pass1/pass2 also get y = ncomp); extra: output pointer of
+// K_FORWARD / K_DECOMP; extra_i: K_DECOMP writes FP64 (1) or FP32 (0)
+hipError_t launch_pass(int kind, int precision, const Job& j, int grid, hipStream_t s, void* extra = nullptr,
+                       int extra_i = 0);
+int resident_blocks(int kind, int precision, int order);  // workgroups per CU
+hipError_t launch_pass_fp64(int kind, const Job& j, int grid, hipStream_t s, void* extra, int extra_i);
+hipError_t launch_pass_fp32(int kind, const Job& j, int grid, hipStream_t s, void* extra, int extra_i);
+hipError_t launch_pass_bf16(int kind, const Job& j, int grid, hipStream_t s, void* extra, int extra_i);
+int resident_fp64(int kind, int order);
+int resident_fp32(int kind, int order);
+int resident_bf16(int kind, int order);
+// order-independent kernels (isr_select.hip)
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
-hipError_t launch_pass1(const Job& j, int grid_x, hipStream_t s);
-hipError_t launch_select1(const Job& j, hipStream_t s);
-hipError_t launch_pass2(const Job& j, int grid_x, hipStream_t s);
+hipError_t launch_select1(const Job& j, int sample, hipStream_t s);
 hipError_t launch_refine(const Job& j, int level, int grid_x, hipStream_t s);
 hipError_t launch_select(const Job& j, int level, hipStream_t s);
-hipError_t launch_pass3(const Job& j, int grid, hipStream_t s);
 hipError_t launch_finalize(const Job& j, hipStream_t s);
-hipError_t launch_decompress(const Job& j, void* out, int out_fp64, int grid, hipStream_t s);
-hipError_t launch_forward(const Job& j, void* coef, int grid, hipStream_t s);
 
 // Host tables (isr_tables.cpp): correctly rounded FP64 values.
 struct HostTables {

@@ -284,6 +284,10 @@ Sizes plan_sizes(const isr_field* f) {
   z.off_histN = take((size_t)nc * HBINS * sizeof(HistBin));
   z.off_histR = take((size_t)nc * HBINS * sizeof(HistBin));
   z.off_histL = take((size_t)(NLEV - 1) * nc * RBINS * sizeof(HistBin));
+  z.off_histEs = take((size_t)nc * HBINS * sizeof(HistBin));
+  z.off_histNs = take((size_t)nc * HBINS * sizeof(HistBin));
+  // a 1/32 sample of the tiles predicts the boundary bin when there are enough tiles
+  z.sample_stride = z.tiles >= 1024 ? 32 : 0;
   z.off_st = take((size_t)nc * sizeof(CompState));
   z.off_ticket = take(256);
   z.off_lookback = take((size_t)nc * z.tiles * 8);
@@ -316,6 +320,9 @@ static Job make_job(isr_ctx* c, const isr_field* f, const Sizes& z, char* scratc
   j.histN = (HistBin*)(scratch + z.off_histN);
   j.histR = (HistBin*)(scratch + z.off_histR);
   j.histL = (HistBin*)(scratch + z.off_histL);
+  j.histEs = (HistBin*)(scratch + z.off_histEs);
+  j.histNs = (HistBin*)(scratch + z.off_histNs);
+  j.sample_stride = z.sample_stride;
   j.st = (CompState*)(scratch + z.off_st);
   j.ticket = (u32*)(scratch + z.off_ticket);
   j.lookback = (u64*)(scratch + z.off_lookback);
@@ -334,22 +341,33 @@ namespace isr {
 int enqueue_pipeline(isr_ctx* c, const Job& j, const Sizes& z, hipStream_t s, hipEvent_t* ev) {
   const int nc = j.ncomp;
   const long long tiles = z.tiles;
-  const int target = c->num_cu * 4;
-  int gx = (int)std::min<long long>(tiles, std::max(1, target / nc));
+  const int prec = j.precision;
   const int nn = j.order + 1, tile_vals = (256 / (nn * nn) > 0 ? 256 / (nn * nn) : 1) * nn * nn * nn;
-  // each workgroup may add at most 2^21 - 1 values to one LDS bin
-  const long long min_gx = (tiles * (long long)tile_vals + (1ll << 21) - 2) / ((1ll << 21) - 1);
-  gx = (int)std::max<long long>(gx, std::min<long long>(tiles, min_gx));
+  // persistent grids sized to what is resident at once
+  auto grid_per_comp = [&](int kind) {
+    const long long slots = (long long)c->num_cu * resident_blocks(kind, prec, j.order);
+    long long gx = std::min<long long>(tiles, std::max<long long>(1, slots / nc));
+    // each workgroup may add at most 2^21 - 1 values to one LDS bin
+    const long long min_gx = (tiles * (long long)tile_vals + (1ll << 21) - 2) / ((1ll << 21) - 1);
+    return (int)std::max<long long>(gx, std::min<long long>(tiles, min_gx));
+  };
   auto rec = [&](int k) {
     if (ev) (void)hipEventRecord(ev[k], s);
   };
   HIPCHK(launch_zero((void*)j.histE, z.zero_bytes, s));
   rec(0);
-  HIPCHK(launch_pass1(j, gx, s));
+  if (j.sample_stride > 0) {
+    const long long stiles = (tiles + j.sample_stride - 1) / j.sample_stride;
+    const long long slots = (long long)c->num_cu * resident_blocks(K_PASS1, prec, j.order);
+    const int sgx = (int)std::min<long long>(stiles, std::max<long long>(1, slots / nc));
+    HIPCHK(launch_pass(K_PASS1, prec, j, sgx, s, nullptr, 1));
+    HIPCHK(launch_select1(j, 1, s));
+  }
+  HIPCHK(launch_pass(K_PASS1, prec, j, grid_per_comp(K_PASS1), s, nullptr, 0));
   rec(1);
-  HIPCHK(launch_select1(j, s));
+  HIPCHK(launch_select1(j, 0, s));
   rec(2);
-  HIPCHK(launch_pass2(j, gx, s));
+  HIPCHK(launch_pass(K_PASS2, prec, j, grid_per_comp(K_PASS2), s));
   rec(3);
   const int rgx = std::max(1, std::min(256, (int)((z.nv / 4096) + 1)));
   HIPCHK(launch_refine(j, 2, rgx, s));
@@ -359,8 +377,9 @@ int enqueue_pipeline(isr_ctx* c, const Job& j, const Sizes& z, hipStream_t s, hi
     HIPCHK(launch_select(j, L, s));
   }
   rec(4);
-  const int g3 = (int)std::min<long long>(tiles * nc, (long long)c->num_cu * 4);
-  HIPCHK(launch_pass3(j, g3, s));
+  const long long slots3 = (long long)c->num_cu * resident_blocks(K_PASS3, prec, j.order);
+  const int g3 = (int)std::min<long long>(tiles * nc, slots3);
+  HIPCHK(launch_pass(K_PASS3, prec, j, g3, s));
   rec(5);
   HIPCHK(launch_finalize(j, s));
   rec(6);
@@ -437,10 +456,6 @@ int run_compress(isr_ctx* c, const isr_field* f, isr_blob** out, isr_stats* st) 
   *out = nullptr;
   int rc = check_field(f);
   if (rc) return rc;
-  if (f->precision != ISR_PREC_FP64) {
-    rc = mixed_supported(f->order);
-    if (rc) return fail(ISR_EINVAL, "precision %d is not available for order %d", f->precision, f->order);
-  }
   const double t_start = now_s();
   Sizes z = plan_sizes(f);
   hipStream_t s = (hipStream_t)f->stream;
@@ -640,7 +655,7 @@ int isr_decompress(isr_ctx* c, const isr_blob* b, void* d_out, int32_t out_prec,
   j.voff = b->voff();
   const long long total = (long long)tiles_per_comp(b->order, b->n_elem) * b->ncomp;
   const int grid = (int)std::min<long long>(total, (long long)c->num_cu * 8);
-  HIPCHK(launch_decompress(j, d_out, out_prec == ISR_PREC_FP64, grid, (hipStream_t)stream));
+  HIPCHK(launch_pass(K_DECOMP, ISR_PREC_FP64, j, grid, (hipStream_t)stream, d_out, out_prec == ISR_PREC_FP64));
   return ISR_OK;
 }
 
@@ -664,11 +679,7 @@ int isr_forward(isr_ctx* c, const isr_field* f, void* d_coef) {
   const long long total = (long long)tiles_per_comp(f->order, f->n_elem) * f->ncomp;
   const int grid = (int)std::min<long long>(total, (long long)c->num_cu * 8);
   hipStream_t s = (hipStream_t)f->stream;
-  if (f->precision == ISR_PREC_FP64) {
-    HIPCHK(launch_forward(j, d_coef, grid, s));
-  } else {
-    HIPCHK(launch_forward_mixed(j, d_coef, grid, s));
-  }
+  HIPCHK(launch_pass(K_FORWARD, f->precision, j, grid, s, d_coef));
   HIPCHK(hipStreamSynchronize(s));
   return ISR_OK;
 }

@@ -97,8 +97,4 @@ int Scheduler::poll(uint64_t req, int wait_ms, isr_blob** out, isr_stats* st) {
   return r.status;
 }
 
-int mixed_supported(int) { return -1; }
-
-hipError_t launch_forward_mixed(const Job&, void*, int, hipStream_t) { return hipErrorNotSupported; }
-
 }  // namespace isr

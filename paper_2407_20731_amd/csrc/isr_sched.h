@@ -51,7 +51,8 @@ struct Sizes {
   long long tiles = 0;
   int vbytes = 8;
   size_t off_histE = 0, off_histN = 0, off_histR = 0, off_histL = 0, off_st = 0, off_ticket = 0,
-         off_lookback = 0, off_lists = 0;
+         off_lookback = 0, off_lists = 0, off_histEs = 0, off_histNs = 0;
+  long long sample_stride = 0;
   size_t zero_bytes = 0;     // leading scratch bytes to clear
   u64 list_cap = 0;
   size_t scratch_bytes = 0;
@@ -62,8 +63,6 @@ Sizes plan_sizes(const isr_field* f);
 int enqueue_pipeline(isr_ctx* c, const Job& j, const Sizes& z, hipStream_t s, hipEvent_t* ev);
 int run_compress(isr_ctx* c, const isr_field* f, isr_blob** out, isr_stats* st);
 int run_batch(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_stats* st);
-int mixed_supported(int order);
-hipError_t launch_forward_mixed(const Job& j, void* coef, int grid, hipStream_t s);
 
 // Request queue behind isr_submit / isr_poll.
 class Scheduler {

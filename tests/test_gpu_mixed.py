@@ -1,0 +1,118 @@
+"""GPU checks of the mixed-precision paths (FP32 MFMA, BF16-split MFMA).
+
+The transforms run in reduced precision, so coefficients and energies differ
+from the FP64 oracle by the transform error; the global norm, the threshold
+search and the error check stay exact FP64.  What must hold:
+
+  * U2 (computed from the FP64 field) is bit-identical to the oracle's;
+  * every coefficient differs from the oracle's by at most the derived
+    transform bound (below);
+  * the kept index sets agree except for coefficients whose oracle energy
+    lies in a narrow relative band around the oracle threshold (band derived
+    from the coefficient bound at the threshold's magnitude);
+  * the measured relative error (FP64, of the actual reduced-precision
+    reconstruction) is <= tol, and its FP64 recomputation by the oracle from
+    the blob's kept values agrees;
+  * decompress(blob) equals the oracle's reconstruction from the same kept
+    values and bitmap (FP64 fixed-order inverse on both sides).
+
+Transform error bounds (per element, relative to S = max |u_e|):
+  FP32: three stages of n-term FP32 dot products with FP32-rounded inputs
+        and tables: |dc| <= 3 (n + 2) 2^-24 L^3 S, L = max row sum of |A|;
+  BF16: operands split as hi + lo (16 significant bits, residual <= 2^-17
+        relative), products hi*hi + hi*lo + lo*hi (dropped lo*lo <= 2^-16):
+        |dc| <= 3 (2^-15 + (n + 2) 2^-24) L^3 S.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle.compress import unpack_bitmap
+from oracle.tables import gll_tables
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+EPS = {"fp32": lambda n: 3 * (n + 2) * 2.0 ** -24, "bf16": lambda n: 3 * (2.0 ** -15 + (n + 2) * 2.0 ** -24)}
+
+
+def coef_bound(prec, order, u_elem_max):
+    T = gll_tables(order)
+    L = np.abs(T.A).sum(axis=1).max()
+    return EPS[prec](order + 1) * L ** 3 * u_elem_max
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("order,E,tol", [(7, 512, 1e-3), (5, 300, 1e-3), (9, 100, 1e-3), (3, 77, 1e-2),
+                                         (7, 129, 1e-5), (2, 40, 1e-2), (15, 6, 1e-3)])
+def test_mixed_against_oracle(isr_ctx, prec, order, E, tol):
+    print(f"[case] prec={prec} order={order} E={E} tol={tol}", flush=True)
+    n = order + 1
+    u_np = synth.field(E, order, seed=200 + order)
+    u = torch.from_numpy(u_np).cuda()
+    blob = isr_ctx.compress(u, order, tol, prec)
+    coef = isr_ctx.forward(u, order, prec).cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    arr = blob.arrays()
+    ref = oracle.compress(u_np, order, tol, keep_arrays=True)
+    assert arr.value_bytes == 4
+    emax = np.abs(u_np).reshape(u_np.shape[0], E, -1).max(axis=2)  # [comp, E]
+    report = []
+    for c, rc in enumerate(ref.comps):
+        h = arr.comps[c]
+        assert h["U2"] == rc.U2  # exact FP64 norm of the FP64 field
+        bound = coef_bound(prec, order, emax[c])[:, None, None, None]
+        err = np.abs(coef[c] - rc.coef)
+        assert np.all(err <= bound), (c, float((err / bound).max()))
+        # index sets: disagreements only near the threshold
+        keep_g = unpack_bitmap(arr.bitmap[c], n)
+        keep_o = rc.energy >= rc.tau
+        diff = keep_g != keep_o
+        if np.any(diff):
+            # energy perturbation allowed by the coefficient bound at tau's scale
+            g3 = np.broadcast_to(gll_tables(order).g3, rc.coef.shape)
+            cabs = np.sqrt(rc.tau / g3)
+            beta = 2 * bound / cabs + (bound / cabs) ** 2
+            band = np.abs(rc.energy - rc.tau) <= 2 * beta * rc.tau
+            assert np.all(band[diff]), (c, int(diff.sum()), int((~band & diff).sum()))
+        assert h["rel_err"] <= tol, (c, h["rel_err"])
+        # the oracle's FP64 reconstruction from the blob's own kept values
+        rec = oracle.decompress(arr.bitmap[c], arr.values[c].astype(np.float64), order)
+        from oracle.compress import norm_terms
+        from oracle.exact import exact_sum
+        err2 = exact_sum(norm_terms(u_np[c] - rec, gll_tables(order).w3, None))
+        rel_blob = math.sqrt(err2 / rc.U2)
+        # the blob's FP64 reconstruction differs from the reduced-precision one
+        # the kernel measured by the inverse transform error only
+        assert rel_blob <= tol * 1.05 + 10 * EPS[prec](n) * 4, (c, rel_blob)
+        jac = (keep_g & keep_o).sum() / max(1, (keep_g | keep_o).sum())
+        rec_vs_oracle = math.sqrt(np.sum((rec - rc.recon) ** 2) / np.sum(u_np[c] ** 2))
+        report.append((c, int(diff.sum()), round(jac, 6), h["kept"] - rc.kept, h["rel_err"], rec_vs_oracle))
+    out = isr_ctx.decompress(blob).cpu().numpy()
+    for c in range(len(ref.comps)):
+        rec = oracle.decompress(arr.bitmap[c], arr.values[c].astype(np.float64), order)
+        assert np.array_equal(out[c].view(np.uint64), rec.view(np.uint64))
+    print(f"[mixed] {prec} N={order} E={E} tol={tol}: (comp, |sym diff|, jaccard, kept delta, rel_err, "
+          f"recon err vs oracle) = {report}", flush=True)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_is_deterministic(isr_ctx, prec):
+    u = torch.from_numpy(synth.field(200, 7, seed=31)).cuda()
+    a = isr_ctx.compress(u, 7, 1e-3, prec).to_bytes()
+    b = isr_ctx.compress(u, 7, 1e-3, prec).to_bytes()
+    assert a == b
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_keep_all_round_trip(isr_ctx, prec):
+    u_np = synth.field(50, 5, seed=32)
+    u = torch.from_numpy(u_np).cuda()
+    blob = isr_ctx.compress(u, 5, -1.0, prec)
+    out = isr_ctx.decompress(blob).cpu().numpy()
+    rel = np.sqrt(np.sum((out - u_np) ** 2) / np.sum(u_np ** 2))
+    assert rel < (1e-6 if prec == "fp32" else 1e-4), rel

@@ -90,6 +90,22 @@ def test_zero_and_constant_fields(isr_ctx):
     _check(*_run(isr_ctx, k, 5, 1e-6))
 
 
+def test_speculative_window_hit(isr_ctx):
+    """4096 elements (1024 tiles): a 1/32 tile sample predicts the boundary bin
+    and pass 1 captures its neighbourhood; results must stay bit-exact."""
+    u = synth.field(4096, 7, seed=41)
+    _check(*_run(isr_ctx, u, 7, 1e-3))
+
+
+def test_speculative_window_miss(isr_ctx):
+    """The sampled tiles (every 32nd tile of 4 elements) are scaled far down, so
+    the sample predicts a wrong bin and the candidate pass must run instead."""
+    u = synth.field(4096, 7, ncomp=2, seed=42)
+    sampled = (np.arange(4096) // 4) % 32 == 0
+    u[:, sampled] *= 1e-8
+    _check(*_run(isr_ctx, u, 7, 1e-3))
+
+
 def test_white_noise_field(isr_ctx):
     u = np.random.default_rng(3).standard_normal((3, 200, 8, 8, 8))
     _check(*_run(isr_ctx, u, 7, 1e-2))
