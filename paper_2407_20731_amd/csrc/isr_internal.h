@@ -30,15 +30,15 @@ constexpr int WIN = 256;
 constexpr int WIN_HEAD = 16;  // bins kept above the first tile's largest exponent
 
 // Refinement of the threshold inside the boundary exponent bin: the 52
-// fraction bits are resolved 12 at a time (bits 51..40, 39..28, 27..16,
-// 15..4), then 4 (bits 3..0).  Levels are numbered 2..6; level 1 is the
+// fraction bits are resolved 11 at a time (bits 51..41, 40..30, 29..19,
+// 18..8), then 8 (bits 7..0).  Levels are numbered 2..6; level 1 is the
 // exponent.
-constexpr int RBINS = 4096;
+constexpr int RBINS = 2048;
 constexpr int NLEV = 6;
 constexpr int CAP = 4096;  // a sub-bin with at most CAP members is resolved by sorting
 
-__host__ __device__ constexpr int level_shift(int L) { return L == 6 ? 0 : 40 - 12 * (L - 2); }
-__host__ __device__ constexpr int level_bits(int L) { return L == 6 ? 4 : 12; }
+__host__ __device__ constexpr int level_shift(int L) { return L == 6 ? 0 : 41 - 11 * (L - 2); }
+__host__ __device__ constexpr int level_bits(int L) { return L == 6 ? 8 : 11; }
 
 // Per-component selection state, written by the select kernels.
 struct alignas(256) CompState {
@@ -113,6 +113,36 @@ struct Job {
   void* values;        // kept values, component after component
   u64* voff;           // [ncomp] offset of each component's first value
 };
+
+// Persistent batch launch (isr_batch.cuh): phases of the shared work queue.
+enum BatchPhase {
+  PH_P0 = 0, PH_S0, PH_P1, PH_S1, PH_P2,
+  PH_R2, PH_S2, PH_R3, PH_S3, PH_R4, PH_S4, PH_R5, PH_S5, PH_R6, PH_S6,
+  PH_P3, PH_FIN, NPH
+};
+struct BatchCtl {
+  const Job* jobs;          // [nsnap], device
+  const int* pair_snap;     // [npairs] snapshot of each (snapshot, component) pair
+  const int* pair_comp;     // [npairs]
+  const long long* items;   // [NPH][npairs + 1]: prefix of item counts over pairs
+  long long phase_off[NPH + 1];  // first ticket of each phase
+  int npairs;
+  u32* done;                // [NPH][npairs] completed items
+  unsigned long long* ticket;
+  int* err;                 // a bounded wait expired
+};
+hipError_t launch_batch(int precision, const BatchCtl& B, int grid, size_t lds_bytes, hipStream_t s);
+size_t batch_lds(int precision);
+int batch_resident(int precision, size_t lds_bytes);
+hipError_t launch_batch_fp64(const BatchCtl& B, int grid, size_t lds, hipStream_t s);
+hipError_t launch_batch_fp32(const BatchCtl& B, int grid, size_t lds, hipStream_t s);
+hipError_t launch_batch_bf16(const BatchCtl& B, int grid, size_t lds, hipStream_t s);
+size_t batch_lds_fp64();
+size_t batch_lds_fp32();
+size_t batch_lds_bf16();
+int batch_resident_fp64(size_t lds);
+int batch_resident_fp32(size_t lds);
+int batch_resident_bf16(size_t lds);
 
 // Streaming passes (isr_passes.cuh), one instantiation file per precision.
 enum PassKind { K_PASS1 = 0, K_PASS2 = 1, K_PASS3 = 2, K_DECOMP = 3, K_FORWARD = 4 };

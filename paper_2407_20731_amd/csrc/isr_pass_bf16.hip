@@ -1,4 +1,6 @@
-// Streaming passes instantiated for the BF16 transform path, orders 1..15.
+// Streaming passes and the persistent batch kernel instantiated for the
+// BF16 transform path.
+#include "isr_batch.cuh"
 #include "isr_passes.cuh"
 
 namespace isr {
@@ -8,5 +10,13 @@ hipError_t launch_pass_bf16(int kind, const Job& j, int grid, hipStream_t s, voi
 }
 
 int resident_bf16(int kind, int order) { return resident_prec<P_BF16>(kind, order); }
+
+hipError_t launch_batch_bf16(const BatchCtl& B, int grid, size_t lds, hipStream_t s) {
+  return launch_batch_prec<P_BF16>(B, grid, lds, s);
+}
+
+size_t batch_lds_bf16() { return batch_lds_prec<P_BF16>(); }
+
+int batch_resident_bf16(size_t lds) { return batch_resident_prec<P_BF16>(lds); }
 
 }  // namespace isr

@@ -316,25 +316,32 @@ DEV void cbuf_put(u64* cbuf, u32* ncb, bool m, u64 key) {
 }
 
 template <int N, int PREC>
-__global__ __launch_bounds__(Shape<N>::THREADS) void k_pass1(Job j, int sample) {
+struct Pass1Lds {
+  typedef Shape<N> S;
+  typedef typename XfSel<N, PREC>::type X;
+  static constexpr int CB1 = S::TILE + 512;  // room for one whole tile above the flush mark
+  double su[S::TILE];
+  typename X::work_t sw_buf[PREC == P_FP64 ? 1 : S::TILE];
+  LdsHist hN, hE;
+  typename X::Smem sm;
+  u64 cbuf[CB1];
+  u32 ncb;
+  u64 gbase_s;
+};
+
+// Tiles t0, t0 + tstride, ... of component comp.
+template <int N, int PREC>
+DEV void pass1_body(const Job& j, int comp, long long t0, long long tstride, int sample, Pass1Lds<N, PREC>& L) {
   typedef Shape<N> S;
   typedef typename XfSel<N, PREC>::type X;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, EPI = S::EPI, T = S::THREADS;
   constexpr bool INPLACE = PREC == P_FP64;
-  constexpr int CB1 = S::TILE + 512;  // room for one whole tile above the flush mark
-  __shared__ double su[S::TILE];
-  __shared__ typename X::work_t sw_buf[INPLACE ? 1 : S::TILE];
-  __shared__ LdsHist hN, hE;
-  __shared__ typename X::Smem sm;
-  __shared__ u64 cbuf[CB1];
-  __shared__ u32 ncb;
-  __shared__ u64 gbase_s;
+  constexpr int CB1 = Pass1Lds<N, PREC>::CB1;
   typename X::Regs rg;
-  const int tid = threadIdx.x, comp = blockIdx.y;
+  const int tid = threadIdx.x;
   const int el = tid / n2, a = (tid % n2) / n, b = tid % n;
   const long long E = j.n_elem;
   const long long tiles = (E + EPI - 1) / EPI;
-  const long long tstep = sample ? j.sample_stride : 1;
   const double* u = j.u + (size_t)comp * j.comp_stride;
   CompState* st = j.st + comp;
   HistBin* gN = (sample ? j.histNs : j.histN) + (size_t)comp * HBINS;
@@ -342,25 +349,26 @@ __global__ __launch_bounds__(Shape<N>::THREADS) void k_pass1(Job j, int sample) 
   const int wlo = sample ? 0 : st->win_lo, whi = sample ? 0 : st->win_hi;  // [wlo, whi)
   const bool capture = wlo < whi;
   u64* list = j.lists + ((size_t)comp * 2 + 0) * j.list_cap;
-  typename X::work_t* sw = INPLACE ? (typename X::work_t*)su : sw_buf;
-  lh_init(hN, tid, T);
-  lh_init(hE, tid, T);
-  X::init(sm, rg, j.tab, tid, T);
-  if (tid == 0) ncb = 0u;
+  typename X::work_t* sw = INPLACE ? (typename X::work_t*)L.su : L.sw_buf;
+  __syncthreads();
+  lh_init(L.hN, tid, T);
+  lh_init(L.hE, tid, T);
+  X::init(L.sm, rg, j.tab, tid, T);
+  if (tid == 0) L.ncb = 0u;
   Prefetch<T, S::TILE> pf;
-  long long t = (long long)blockIdx.x * tstep;
+  long long t = t0;
   if (t < tiles) {
     const long long e0 = t * EPI;
     pf.load(u + e0 * n3, (int)((E - e0) < EPI ? (E - e0) : EPI) * n3, tid);
   }
   bool first = true;
-  for (; t < tiles; t += (long long)gridDim.x * tstep) {
+  for (; t < tiles; t += tstride) {
     const long long e0 = t * EPI;
     const int ne = (int)((E - e0) < EPI ? (E - e0) : EPI);
     __syncthreads();
-    pf.store(su, ne * n3, tid);
+    pf.store(L.su, ne * n3, tid);
     __syncthreads();
-    const long long tn = t + (long long)gridDim.x * tstep;
+    const long long tn = t + tstride;
     if (tn < tiles) {
       const long long e1 = tn * EPI;
       pf.load(u + e1 * n3, (int)((E - e1) < EPI ? (E - e1) : EPI) * n3, tid);
@@ -370,7 +378,7 @@ __global__ __launch_bounds__(Shape<N>::THREADS) void k_pass1(Job j, int sample) 
     // norm terms (J_e * w3[k][j][i]) * (u*u) of pencil (k=a, j=b)
     double nt[n];
     if (act) {
-      const double* pin = su + el * n3 + (a * n + b) * n;
+      const double* pin = L.su + el * n3 + (a * n + b) * n;
       const double* w3 = j.tab.w3 + (a * n + b) * n;
 #pragma unroll
       for (int i = 0; i < n; ++i) nt[i] = jw(j.jac, e, w3[i]) * (pin[i] * pin[i]);
@@ -378,19 +386,19 @@ __global__ __launch_bounds__(Shape<N>::THREADS) void k_pass1(Job j, int sample) 
     if (first) {
       if (act) {
 #pragma unroll
-        for (int i = 0; i < n; ++i) lh_note_max(hN, nt[i]);
+        for (int i = 0; i < n; ++i) lh_note_max(L.hN, nt[i]);
       }
       __syncthreads();
-      if (tid == 0) lh_place(hN);
+      if (tid == 0) lh_place(L.hN);
       __syncthreads();
     }
     if (act) {
 #pragma unroll
-      for (int i = 0; i < n; ++i) lh_insert(hN, gN, nt[i]);
+      for (int i = 0; i < n; ++i) lh_insert(L.hN, gN, nt[i]);
     }
     __syncthreads();
     double c[n], en[n];
-    X::forward(su, sw, sm, rg, el, a, b, act, ne, c);
+    X::forward(L.su, sw, L.sm, rg, el, a, b, act, ne, c);
     if (act) {
 #pragma unroll
       for (int r = 0; r < n; ++r) en[r] = jw(j.jac, e, j.tab.g3[(r * n + a) * n + b]) * (c[r] * c[r]);
@@ -398,51 +406,65 @@ __global__ __launch_bounds__(Shape<N>::THREADS) void k_pass1(Job j, int sample) 
     if (first) {
       if (act) {
 #pragma unroll
-        for (int r = 0; r < n; ++r) lh_note_max(hE, en[r]);
+        for (int r = 0; r < n; ++r) lh_note_max(L.hE, en[r]);
       }
       __syncthreads();
-      if (tid == 0) lh_place(hE);
+      if (tid == 0) lh_place(L.hE);
       __syncthreads();
       first = false;
     }
     if (act) {
 #pragma unroll
-      for (int r = 0; r < n; ++r) lh_insert(hE, gE, en[r]);
+      for (int r = 0; r < n; ++r) lh_insert(L.hE, gE, en[r]);
     }
     if (capture) {
 #pragma unroll
       for (int r = 0; r < n; ++r) {
         const u64 key = act ? dbits(en[r]) : 0ull;
         const int ex = bits_exp(key);
-        cbuf_put(cbuf, &ncb, act && ex >= wlo && ex < whi, key);
+        cbuf_put(L.cbuf, &L.ncb, act && ex >= wlo && ex < whi, key);
       }
       __syncthreads();
-      if (ncb > (u32)(CB1 - S::TILE))
-        cbuf_flush(cbuf, &ncb, &gbase_s, list, &st->list_count[0], j.list_cap, &st->flags, tid, T);
+      if (L.ncb > (u32)(CB1 - S::TILE))
+        cbuf_flush(L.cbuf, &L.ncb, &L.gbase_s, list, &st->list_count[0], j.list_cap, &st->flags, tid, T);
     }
   }
   __syncthreads();
-  lh_flush(hN, gN, tid, T);
-  lh_flush(hE, gE, tid, T);
-  if (capture) cbuf_flush(cbuf, &ncb, &gbase_s, list, &st->list_count[0], j.list_cap, &st->flags, tid, T);
+  lh_flush(L.hN, gN, tid, T);
+  lh_flush(L.hE, gE, tid, T);
+  if (capture) cbuf_flush(L.cbuf, &L.ncb, &L.gbase_s, list, &st->list_count[0], j.list_cap, &st->flags, tid, T);
+  __syncthreads();
+}
+
+template <int N, int PREC>
+__global__ __launch_bounds__(Shape<N>::THREADS) void k_pass1(Job j, int sample) {
+  __shared__ Pass1Lds<N, PREC> L;
+  const long long tstep = sample ? j.sample_stride : 1;
+  pass1_body<N, PREC>(j, blockIdx.y, (long long)blockIdx.x * tstep, (long long)gridDim.x * tstep, sample, L);
 }
 
 // ---- pass 2 (only when the boundary bin fell outside the captured window) ----
 template <int N, int PREC>
-__global__ __launch_bounds__(Shape<N>::THREADS) void k_pass2(Job j) {
+struct Pass2Lds {
+  typedef Shape<N> S;
+  typedef typename XfSel<N, PREC>::type X;
+  double su[S::TILE];
+  typename X::work_t sw_buf[PREC == P_FP64 ? 1 : S::TILE];
+  typename X::Smem sm;
+  u64 cbuf[CBUF];
+  u32 ncb;
+  u64 gbase_s;
+};
+
+template <int N, int PREC>
+DEV void pass2_body(const Job& j, int comp, long long t0, long long tstride, Pass2Lds<N, PREC>& L) {
   typedef Shape<N> S;
   typedef typename XfSel<N, PREC>::type X;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, EPI = S::EPI, T = S::THREADS;
   constexpr bool INPLACE = PREC == P_FP64;
   static_assert(S::TILE <= CBUF, "a whole tile must fit the candidate buffer");
-  __shared__ double su[S::TILE];
-  __shared__ typename X::work_t sw_buf[INPLACE ? 1 : S::TILE];
-  __shared__ typename X::Smem sm;
-  __shared__ u64 cbuf[CBUF];
-  __shared__ u32 ncb;
-  __shared__ u64 gbase_s;
   typename X::Regs rg;
-  const int tid = threadIdx.x, comp = blockIdx.y;
+  const int tid = threadIdx.x;
   CompState* st = j.st + comp;
   if (st->resolved || !st->need_pass2) return;
   const u64 prefix = st->key_prefix, mask = st->key_mask;
@@ -451,22 +473,23 @@ __global__ __launch_bounds__(Shape<N>::THREADS) void k_pass2(Job j) {
   const long long E = j.n_elem;
   const long long tiles = (E + EPI - 1) / EPI;
   const double* u = j.u + (size_t)comp * j.comp_stride;
-  typename X::work_t* sw = INPLACE ? (typename X::work_t*)su : sw_buf;
-  X::init(sm, rg, j.tab, tid, T);
-  if (tid == 0) ncb = 0u;
+  typename X::work_t* sw = INPLACE ? (typename X::work_t*)L.su : L.sw_buf;
+  __syncthreads();
+  X::init(L.sm, rg, j.tab, tid, T);
+  if (tid == 0) L.ncb = 0u;
   Prefetch<T, S::TILE> pf;
-  long long t = blockIdx.x;
+  long long t = t0;
   if (t < tiles) {
     const long long e0 = t * EPI;
     pf.load(u + e0 * n3, (int)((E - e0) < EPI ? (E - e0) : EPI) * n3, tid);
   }
-  for (; t < tiles; t += gridDim.x) {
+  for (; t < tiles; t += tstride) {
     const long long e0 = t * EPI;
     const int ne = (int)((E - e0) < EPI ? (E - e0) : EPI);
     __syncthreads();
-    pf.store(su, ne * n3, tid);
+    pf.store(L.su, ne * n3, tid);
     __syncthreads();
-    const long long tn = t + gridDim.x;
+    const long long tn = t + tstride;
     if (tn < tiles) {
       const long long e1 = tn * EPI;
       pf.load(u + e1 * n3, (int)((E - e1) < EPI ? (E - e1) : EPI) * n3, tid);
@@ -474,7 +497,7 @@ __global__ __launch_bounds__(Shape<N>::THREADS) void k_pass2(Job j) {
     const bool act = tid < S::ACT && el < ne;
     const long long e = e0 + el;
     double c[n];
-    X::forward(su, sw, sm, rg, el, a, b, act, ne, c);
+    X::forward(L.su, sw, L.sm, rg, el, a, b, act, ne, c);
 #pragma unroll
     for (int r = 0; r < n; ++r) {
       u64 key = 0;
@@ -484,168 +507,187 @@ __global__ __launch_bounds__(Shape<N>::THREADS) void k_pass2(Job j) {
         key = dbits(en);
         m = (key & mask) == prefix;
       }
-      const u64 bal = ballot(m);
-      if (bal) {
-        const int leader = __ffsll((long long)bal) - 1;
-        u32 base = 0;
-        if (lane_id() == leader) base = atomicAdd(&ncb, (u32)__popcll(bal));
-        base = (u32)__shfl((int)base, leader);
-        if (m) cbuf[base + (u32)__popcll(bal & ((1ull << lane_id()) - 1ull))] = key;
-      }
+      cbuf_put(L.cbuf, &L.ncb, m, key);
     }
     __syncthreads();
-    if (ncb > (u32)(CBUF - S::TILE))
-      cbuf_flush(cbuf, &ncb, &gbase_s, list, &st->list_count[0], j.list_cap, &st->flags, tid, T);
+    if (L.ncb > (u32)(CBUF - S::TILE))
+      cbuf_flush(L.cbuf, &L.ncb, &L.gbase_s, list, &st->list_count[0], j.list_cap, &st->flags, tid, T);
   }
-  cbuf_flush(cbuf, &ncb, &gbase_s, list, &st->list_count[0], j.list_cap, &st->flags, tid, T);
+  cbuf_flush(L.cbuf, &L.ncb, &L.gbase_s, list, &st->list_count[0], j.list_cap, &st->flags, tid, T);
+}
+
+template <int N, int PREC>
+__global__ __launch_bounds__(Shape<N>::THREADS) void k_pass2(Job j) {
+  __shared__ Pass2Lds<N, PREC> L;
+  pass2_body<N, PREC>(j, blockIdx.y, blockIdx.x, gridDim.x, L);
 }
 
 // ---- pass 3 -----------------------------------------------------------------
 template <int N, int PREC>
-__global__ __launch_bounds__(Shape<N>::THREADS) void k_pass3(Job j) {
+struct Pass3Lds {
+  typedef Shape<N> S;
+  typedef typename XfSel<N, PREC>::type X;
+  double su[S::TILE];
+  typename X::work_t sw[S::TILE];
+  typename X::Smem sm;
+  LdsHist hR;
+  u64 bm[S::EPI * S::W];
+  u32 cntl[S::EPI];
+  u64 excl_s;
+  long long ticket_s;
+};
+
+// One tile t of component comp.  The error histogram window in L.hR belongs
+// to comp and is flushed by the caller; `first` places it.
+template <int N, int PREC>
+DEV void pass3_tile(const Job& j, int comp, long long t, Pass3Lds<N, PREC>& L,
+                    const typename XfSel<N, PREC>::type::Regs& rg, bool& first) {
   typedef Shape<N> S;
   typedef typename XfSel<N, PREC>::type X;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, EPI = S::EPI, T = S::THREADS, W = S::W;
-  __shared__ double su[S::TILE];
-  __shared__ typename X::work_t sw[S::TILE];
-  __shared__ typename X::Smem sm;
-  __shared__ LdsHist hR;
-  __shared__ u64 bm[EPI * W];
-  __shared__ u32 cntl[EPI];
-  __shared__ u64 excl_s;
-  __shared__ long long ticket_s;
-  typename X::Regs rg;
   const int tid = threadIdx.x;
   const int el = tid / n2, a = (tid % n2) / n, b = tid % n;
   const long long E = j.n_elem;
   const long long tiles = (E + EPI - 1) / EPI;
+  const double tau = j.st[comp].tau;
+  const long long e0 = t * EPI;
+  const int ne = (int)((E - e0) < EPI ? (E - e0) : EPI);
+  const double* u = j.u + (size_t)comp * j.comp_stride;
+  {
+    Prefetch<T, S::TILE> pf;
+    pf.load(u + e0 * n3, ne * n3, tid);
+    pf.store(L.su, ne * n3, tid);
+  }
+  for (int k = tid; k < EPI * W; k += T) L.bm[k] = 0ull;
+  __syncthreads();
+  const bool act = tid < S::ACT && el < ne;
+  const long long e = e0 + el;
+  double c[n];
+  bool keep[n];
+  X::forward(L.su, L.sw, L.sm, rg, el, a, b, act, ne, c);
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < n; ++r) {
+      const double en = jw(j.jac, e, j.tab.g3[(r * n + a) * n + b]) * (c[r] * c[r]);
+      keep[r] = en >= tau;
+      if (keep[r]) {
+        const int f = (r * n + a) * n + b;
+        atomicOr(&L.bm[el * W + (f >> 6)], 1ull << (f & 63));
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < EPI) {
+    u32 s = 0;
+    if (tid < ne)
+      for (int w = 0; w < W; ++w) s += (u32)__popcll(L.bm[tid * W + w]);
+    L.cntl[tid] = s;
+  }
+  __syncthreads();
+  u64* lb = j.lookback + (size_t)comp * tiles;
+  if (tid < 64) lookback_publish(lb, t, L.cntl, ne, &L.excl_s);
+  // inverse transform of the kept set and exact error terms (independent of
+  // the prefix, so the look-back has time to settle meanwhile)
+  double et[n];
+  {
+    double cm[n], ut[n];
+#pragma unroll
+    for (int r = 0; r < n; ++r) cm[r] = (act && keep[r]) ? c[r] : 0.0;
+    X::inverse(L.sw, L.sm, rg, el, a, b, act, ne, cm, ut);
+    if (act) {
+      const double* w3 = j.tab.w3 + (a * n + b) * n;
+      const double* pu = L.su + el * n3 + (a * n + b) * n;
+#pragma unroll
+      for (int i = 0; i < n; ++i) {
+        const double d = pu[i] - ut[i];
+        et[i] = jw(j.jac, e, w3[i]) * (d * d);
+      }
+    }
+  }
+  if (first) {
+    if (act) {
+#pragma unroll
+      for (int i = 0; i < n; ++i) lh_note_max(L.hR, et[i]);
+    }
+    __syncthreads();
+    if (tid == 0) lh_place(L.hR);
+    __syncthreads();
+    first = false;
+  }
+  if (act) {
+#pragma unroll
+    for (int i = 0; i < n; ++i) lh_insert(L.hR, j.histR + (size_t)comp * HBINS, et[i]);
+  }
+  if (tid < 64) lookback_wait(lb, t, L.cntl, ne, &j.st[comp].flags, &L.excl_s);
+  __syncthreads();
+  const u64 ex = L.excl_s;
+  u64* gbm = j.bitmap + ((size_t)comp * E + e0) * W;
+  for (int k = tid; k < ne * W; k += T) gbm[k] = L.bm[k];
+  u64* gptr = j.elem_ptr + (size_t)comp * (E + 1);
+  if (tid < ne) {
+    u64 o = ex;
+    for (int k = 0; k < tid; ++k) o += L.cntl[k];
+    gptr[e0 + tid] = o;
+    if (e0 + tid == E - 1) gptr[E] = o + L.cntl[tid];
+  }
+  if (act) {
+    u64 voff;
+    comp_voff(j, comp, voff);
+    u64 eoff = ex;
+    for (int k = 0; k < el; ++k) eoff += L.cntl[k];
+#pragma unroll
+    for (int r = 0; r < n; ++r) {
+      if (!keep[r]) continue;
+      const int f = (r * n + a) * n + b;
+      const int wi = f >> 6;
+      u32 rank = 0;
+      for (int w = 0; w < wi; ++w) rank += (u32)__popcll(L.bm[el * W + w]);
+      rank += (u32)__popcll(L.bm[el * W + wi] & ((1ull << (f & 63)) - 1ull));
+      const u64 pos = voff + eoff + rank;
+      if (j.vbytes == 8)
+        ((double*)j.values)[pos] = c[r];
+      else
+        ((float*)j.values)[pos] = (float)c[r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int N, int PREC>
+__global__ __launch_bounds__(Shape<N>::THREADS) void k_pass3(Job j) {
+  typedef Shape<N> S;
+  typedef typename XfSel<N, PREC>::type X;
+  constexpr int EPI = S::EPI, T = S::THREADS;
+  __shared__ Pass3Lds<N, PREC> L;
+  typename X::Regs rg;
+  const int tid = threadIdx.x;
+  const long long tiles = (j.n_elem + EPI - 1) / EPI;
   const long long total = tiles * j.ncomp;
-  lh_init(hR, tid, T);
-  X::init(sm, rg, j.tab, tid, T);
+  lh_init(L.hR, tid, T);
+  X::init(L.sm, rg, j.tab, tid, T);
   int cur = -1;
   bool first = true;
   for (;;) {
     __syncthreads();
-    if (tid == 0) ticket_s = (long long)atomicAdd(&j.ticket[0], 1u);
+    if (tid == 0) L.ticket_s = (long long)atomicAdd(&j.ticket[0], 1u);
     __syncthreads();
-    const long long tk = ticket_s;
+    const long long tk = L.ticket_s;
     if (tk >= total) break;
     const int comp = (int)(tk / tiles);
-    const long long t = tk % tiles;
     if (comp != cur) {
       if (cur >= 0) {
-        lh_flush(hR, j.histR + (size_t)cur * HBINS, tid, T);
+        lh_flush(L.hR, j.histR + (size_t)cur * HBINS, tid, T);
         __syncthreads();
-        lh_init(hR, tid, T);
+        lh_init(L.hR, tid, T);
         __syncthreads();
       }
       cur = comp;
       first = true;
     }
-    const double tau = j.st[comp].tau;
-    const long long e0 = t * EPI;
-    const int ne = (int)((E - e0) < EPI ? (E - e0) : EPI);
-    const double* u = j.u + (size_t)comp * j.comp_stride;
-    {
-      Prefetch<T, S::TILE> pf;
-      pf.load(u + e0 * n3, ne * n3, tid);
-      pf.store(su, ne * n3, tid);
-    }
-    for (int k = tid; k < EPI * W; k += T) bm[k] = 0ull;
-    __syncthreads();
-    const bool act = tid < S::ACT && el < ne;
-    const long long e = e0 + el;
-    double c[n];
-    bool keep[n];
-    X::forward(su, sw, sm, rg, el, a, b, act, ne, c);
-    if (act) {
-#pragma unroll
-      for (int r = 0; r < n; ++r) {
-        const double en = jw(j.jac, e, j.tab.g3[(r * n + a) * n + b]) * (c[r] * c[r]);
-        keep[r] = en >= tau;
-        if (keep[r]) {
-          const int f = (r * n + a) * n + b;
-          atomicOr(&bm[el * W + (f >> 6)], 1ull << (f & 63));
-        }
-      }
-    }
-    __syncthreads();
-    if (tid < EPI) {
-      u32 s = 0;
-      if (tid < ne)
-        for (int w = 0; w < W; ++w) s += (u32)__popcll(bm[tid * W + w]);
-      cntl[tid] = s;
-    }
-    __syncthreads();
-    u64* lb = j.lookback + (size_t)comp * tiles;
-    if (tid < 64) lookback_publish(lb, t, cntl, ne, &excl_s);
-    // inverse transform of the kept set and exact error terms (independent of
-    // the prefix, so the look-back has time to settle meanwhile)
-    double et[n];
-    {
-      double cm[n], ut[n];
-#pragma unroll
-      for (int r = 0; r < n; ++r) cm[r] = (act && keep[r]) ? c[r] : 0.0;
-      X::inverse(sw, sm, rg, el, a, b, act, ne, cm, ut);
-      if (act) {
-        const double* w3 = j.tab.w3 + (a * n + b) * n;
-        const double* pu = su + el * n3 + (a * n + b) * n;
-#pragma unroll
-        for (int i = 0; i < n; ++i) {
-          const double d = pu[i] - ut[i];
-          et[i] = jw(j.jac, e, w3[i]) * (d * d);
-        }
-      }
-    }
-    if (first) {
-      if (act) {
-#pragma unroll
-        for (int i = 0; i < n; ++i) lh_note_max(hR, et[i]);
-      }
-      __syncthreads();
-      if (tid == 0) lh_place(hR);
-      __syncthreads();
-      first = false;
-    }
-    if (act) {
-#pragma unroll
-      for (int i = 0; i < n; ++i) lh_insert(hR, j.histR + (size_t)comp * HBINS, et[i]);
-    }
-    if (tid < 64) lookback_wait(lb, t, cntl, ne, &j.st[comp].flags, &excl_s);
-    __syncthreads();
-    const u64 ex = excl_s;
-    u64* gbm = j.bitmap + ((size_t)comp * E + e0) * W;
-    for (int k = tid; k < ne * W; k += T) gbm[k] = bm[k];
-    u64* gptr = j.elem_ptr + (size_t)comp * (E + 1);
-    if (tid < ne) {
-      u64 o = ex;
-      for (int k = 0; k < tid; ++k) o += cntl[k];
-      gptr[e0 + tid] = o;
-      if (e0 + tid == E - 1) gptr[E] = o + cntl[tid];
-    }
-    if (act) {
-      u64 voff;
-      comp_voff(j, comp, voff);
-      u64 eoff = ex;
-      for (int k = 0; k < el; ++k) eoff += cntl[k];
-#pragma unroll
-      for (int r = 0; r < n; ++r) {
-        if (!keep[r]) continue;
-        const int f = (r * n + a) * n + b;
-        const int wi = f >> 6;
-        u32 rank = 0;
-        for (int w = 0; w < wi; ++w) rank += (u32)__popcll(bm[el * W + w]);
-        rank += (u32)__popcll(bm[el * W + wi] & ((1ull << (f & 63)) - 1ull));
-        const u64 pos = voff + eoff + rank;
-        if (j.vbytes == 8)
-          ((double*)j.values)[pos] = c[r];
-        else
-          ((float*)j.values)[pos] = (float)c[r];
-      }
-    }
+    pass3_tile<N, PREC>(j, comp, tk % tiles, L, rg, first);
   }
   __syncthreads();
-  if (cur >= 0) lh_flush(hR, j.histR + (size_t)cur * HBINS, tid, T);
+  if (cur >= 0) lh_flush(L.hR, j.histR + (size_t)cur * HBINS, tid, T);
 }
 
 // ---- decompress (FP64 fixed-order inverse) ------------------------------------

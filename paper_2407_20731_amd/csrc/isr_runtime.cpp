@@ -196,6 +196,8 @@ struct isr_ctx {
   std::unique_ptr<isr::Scheduler> sched;
   int max_inflight = 8;
   CompState* st_host = nullptr;  // pinned
+  std::mutex host_mu;            // pool of pinned per-request state buffers
+  std::vector<CompState*> host_all, host_free;
 };
 
 static int set_device(isr_ctx* c) {
@@ -451,99 +453,368 @@ static void fill_stats(isr_blob* b, const CompState* hs, isr_stats* st) {
 
 namespace isr {
 
-// Run one compression to completion on stream s (caller holds ctx->mu).
-int run_compress(isr_ctx* c, const isr_field* f, isr_blob** out, isr_stats* st) {
-  *out = nullptr;
+int ctx_device(const isr_ctx* c) { return c->device; }
+int ctx_max_inflight(const isr_ctx* c) { return c->max_inflight; }
+uint64_t ctx_budget(const isr_ctx* c) { return c->arena->budget(); }
+
+// Footprint a request needs from the arena (scratch + worst-case blob).
+uint64_t request_footprint(const isr_field* f) {
+  Sizes z = plan_sizes(f);
+  return (uint64_t)z.scratch_bytes + z.blob_max + 512;
+}
+
+static CompState* grab_host_state(isr_ctx* c) {
+  std::lock_guard<std::mutex> g(c->host_mu);
+  if (c->host_free.empty()) {
+    CompState* p = nullptr;
+    if (hipHostMalloc((void**)&p, sizeof(CompState) * ISR_MAX_COMP, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    c->host_all.push_back(p);
+    return p;
+  }
+  CompState* p = c->host_free.back();
+  c->host_free.pop_back();
+  return p;
+}
+
+static void put_host_state(isr_ctx* c, CompState* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> g(c->host_mu);
+  c->host_free.push_back(p);
+}
+
+static int task_enqueue(Task* t) {
+  int rc = enqueue_pipeline(t->c, t->j, t->z, t->s, t->timing ? t->ev : nullptr);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(t->hs, t->j.st, sizeof(CompState) * t->f.ncomp, hipMemcpyDeviceToHost, t->s));
+  HIPCHK(hipEventRecord(t->done, t->s));
+  return ISR_OK;
+}
+
+void task_release(Task* t) {
+  if (t->scratch) t->c->arena->free(t->scratch);
+  t->scratch = nullptr;
+  if (t->b) {
+    t->c->arena->free(t->b->dev);
+    delete t->b;
+    t->b = nullptr;
+  }
+  if (t->done) (void)hipEventDestroy(t->done);
+  t->done = nullptr;
+  if (t->timing)
+    for (auto& e : t->ev) (void)hipEventDestroy(e);
+  t->timing = false;
+  put_host_state(t->c, t->hs);
+  t->hs = nullptr;
+}
+
+// Validate, allocate and enqueue the whole pipeline on stream s.  ISR_ENOMEM
+// when the request does not fit the HBM budget right now.
+int task_begin(isr_ctx* c, const isr_field* f, hipStream_t s, bool timing, Task* t) {
   int rc = check_field(f);
   if (rc) return rc;
-  const double t_start = now_s();
-  Sizes z = plan_sizes(f);
-  hipStream_t s = (hipStream_t)f->stream;
-  char* scratch = (char*)c->arena->alloc(z.scratch_bytes);
-  if (!scratch) return fail(ISR_ENOMEM, "scratch of %zu bytes does not fit the HBM budget", z.scratch_bytes);
-  isr_blob* b = new_blob(c, f, z);
-  if (!b) {
-    c->arena->free(scratch);
-    return fail(ISR_ENOMEM, "blob of %zu bytes does not fit the HBM budget", z.blob_max);
+  t->c = c;
+  t->f = *f;
+  t->s = s;
+  t->t_start = now_s();
+  t->z = plan_sizes(f);
+  t->scratch = (char*)c->arena->alloc(t->z.scratch_bytes);
+  if (!t->scratch) return fail(ISR_ENOMEM, "scratch of %zu bytes does not fit the HBM budget", t->z.scratch_bytes);
+  t->b = new_blob(c, f, t->z);
+  if (!t->b) {
+    c->arena->free(t->scratch);
+    t->scratch = nullptr;
+    return fail(ISR_ENOMEM, "blob of %zu bytes does not fit the HBM budget", t->z.blob_max);
   }
-  Job j = make_job(c, f, z, scratch, b);
-  const bool timing = (c->flags & ISR_FLAG_TIMING) && st;
-  hipEvent_t ev[7] = {};
+  t->hs = grab_host_state(c);
+  if (!t->hs || hipEventCreateWithFlags(&t->done, hipEventDisableTiming) != hipSuccess) {
+    task_release(t);
+    return fail(ISR_EDEVICE, "could not create host state or event");
+  }
+  t->j = make_job(c, f, t->z, t->scratch, t->b);
+  t->timing = timing;
   if (timing)
-    for (auto& e : ev) (void)hipEventCreate(&e);
-  CompState* hs = c->st_host;
-  int iters = 0;
-  float repair_ms = 0.f;
-  for (;;) {
-    rc = enqueue_pipeline(c, j, z, s, timing ? ev : nullptr);
-    if (rc) break;
-    if (hipMemcpyAsync(hs, j.st, sizeof(CompState) * f->ncomp, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
-      rc = fail(ISR_EDEVICE, "device pipeline failed: %s", hipGetErrorString(hipGetLastError()));
-      break;
-    }
-    int flags = 0;
-    for (int k = 0; k < f->ncomp; ++k) flags |= hs[k].flags;
-    rc = status_from_flags(flags);
-    if (rc) break;
-    if (timing) {
-      float ms[6];
-      for (int k = 0; k < 6; ++k) (void)hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]);
-      if (iters == 0) {
-        st->phase_ms[0] = ms[0];
-        st->phase_ms[1] = ms[1];
-        st->phase_ms[2] = ms[2];
-        st->phase_ms[3] = ms[3];
-        st->phase_ms[4] = ms[4];
-        st->phase_ms[5] = ms[5];
-      } else {
-        for (int k = 0; k < 6; ++k) repair_ms += ms[k];
-      }
-    }
-    // rounding repair: lower B where the measured error exceeds tol
-    bool again = false;
-    if (f->tol >= 0.0 && iters < 4) {
-      for (int k = 0; k < f->ncomp; ++k) {
-        if (hs[k].rel > f->tol) {
-          const double fr = f->tol / hs[k].rel;
-          j.Bov[k] = (hs[k].B * (fr * fr)) * (1.0 - 0x1p-20);
-          again = true;
-        } else {
-          j.Bov[k] = hs[k].B;  // unchanged, reproduces the same result
-        }
-      }
-    }
-    if (!again) break;
-    ++iters;
-  }
-  if (timing) {
-    st->phase_ms[6] = repair_ms;
-    for (auto& e : ev) (void)hipEventDestroy(e);
-  }
-  c->arena->free(scratch);
+    for (auto& e : t->ev) (void)hipEventCreate(&e);
+  std::memset(&t->st, 0, sizeof(t->st));
+  rc = task_enqueue(t);
+  if (rc) task_release(t);
+  return rc;
+}
+
+// After t->done completed: check the result, repair (ISR_PENDING: enqueued
+// again) or finish (final status; the blob moves to *out on OK / ETOL).
+int task_step(Task* t, isr_blob** out) {
+  CompState* hs = t->hs;
+  const isr_field* f = &t->f;
+  int flags = 0;
+  for (int k = 0; k < f->ncomp; ++k) flags |= hs[k].flags;
+  int rc = status_from_flags(flags);
   if (rc) {
-    c->arena->free(b->dev);
-    delete b;
+    task_release(t);
     return rc;
   }
-  fill_stats(b, hs, st);
+  if (t->timing) {
+    float ms[6];
+    for (int k = 0; k < 6; ++k) (void)hipEventElapsedTime(&ms[k], t->ev[k], t->ev[k + 1]);
+    for (int k = 0; k < 6; ++k) {
+      if (t->iters == 0)
+        t->st.phase_ms[k] = ms[k];
+      else
+        t->repair_ms += ms[k];
+    }
+  }
+  // rounding repair: lower B where the measured error exceeds tol
+  bool again = false;
+  if (f->tol >= 0.0 && t->iters < 4) {
+    for (int k = 0; k < f->ncomp; ++k) {
+      if (hs[k].rel > f->tol) {
+        const double fr = f->tol / hs[k].rel;
+        t->j.Bov[k] = (hs[k].B * (fr * fr)) * (1.0 - 0x1p-20);
+        again = true;
+      } else {
+        t->j.Bov[k] = hs[k].B;  // unchanged, reproduces the same result
+      }
+    }
+  }
+  if (again) {
+    ++t->iters;
+    rc = task_enqueue(t);
+    if (rc) {
+      task_release(t);
+      return rc;
+    }
+    return ISR_PENDING;
+  }
+  isr_blob* b = t->b;
+  fill_stats(b, hs, &t->st);
   bool within = true;
   if (f->tol >= 0.0)
     for (int k = 0; k < f->ncomp; ++k) within = within && !(hs[k].rel > f->tol);
   b->status = within ? ISR_OK : ISR_ETOL;
   // return the unused tail of the worst-case value reservation
   const size_t used = 256 + b->bitmap_bytes() + b->ptr_bytes() + b->values_bytes();
-  c->arena->shrink(b->dev, used);
+  t->c->arena->shrink(b->dev, used);
   b->dev_bytes = (used + 255) & ~size_t(255);
-  if (st) {
-    st->repair_iters = iters;
-    st->status = b->status;
-    st->t_start = t_start;
-    st->t_done = now_s();
-  }
+  t->st.phase_ms[6] = t->repair_ms;
+  t->st.repair_iters = t->iters;
+  t->st.status = b->status;
+  t->st.t_start = t->t_start;
+  t->st.t_done = now_s();
+  t->b = nullptr;  // handed over
+  task_release(t);
   *out = b;
-  if (!within) fail(ISR_ETOL, "relative error above tol after %d repairs", iters);
+  if (!within) fail(ISR_ETOL, "relative error above tol after %d repairs", t->iters);
   return b->status;
+}
+
+// Several snapshots of orders 5, 7 and 9 in ONE persistent launch
+// (isr_batch.cuh); other batches run one after another.
+int run_batch(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_stats* st) {
+  if (count <= 0) return ISR_OK;
+  bool persistent = true;
+  for (int i = 0; i < count; ++i) {
+    const int o = fs[i].order;
+    if ((o != 5 && o != 7 && o != 9) || fs[i].precision != fs[0].precision) persistent = false;
+  }
+  if (!persistent) return run_batch_sequential(c, fs, count, outs, st);
+  const int prec = fs[0].precision;
+  hipStream_t s = (hipStream_t)fs[0].stream;
+  const double t_start = now_s();
+  struct Snap {
+    Sizes z;
+    char* scratch = nullptr;
+    isr_blob* b = nullptr;
+    Job j;
+    CompState* hs = nullptr;
+  };
+  std::vector<Snap> sn(count);
+  auto cleanup = [&]() {
+    for (auto& x : sn) {
+      if (x.scratch) c->arena->free(x.scratch);
+      if (x.b) {
+        c->arena->free(x.b->dev);
+        delete x.b;
+      }
+      put_host_state(c, x.hs);
+      x = Snap();
+    }
+  };
+  for (int i = 0; i < count; ++i) {
+    outs[i] = nullptr;
+    Snap& x = sn[i];
+    x.z = plan_sizes(&fs[i]);
+    x.scratch = (char*)c->arena->alloc(x.z.scratch_bytes);
+    x.b = x.scratch ? new_blob(c, &fs[i], x.z) : nullptr;
+    x.hs = grab_host_state(c);
+    if (!x.scratch || !x.b || !x.hs) {
+      cleanup();
+      return fail(ISR_ENOMEM, "batch of %d snapshots does not fit the HBM budget", count);
+    }
+    x.j = make_job(c, &fs[i], x.z, x.scratch, x.b);
+  }
+  // pairs and items of every phase
+  std::vector<int> psnap, pcomp;
+  for (int i = 0; i < count; ++i)
+    for (int cc = 0; cc < fs[i].ncomp; ++cc) {
+      psnap.push_back(i);
+      pcomp.push_back(cc);
+    }
+  const int np = (int)psnap.size();
+  std::vector<long long> items((size_t)NPH * (np + 1), 0);
+  BatchCtl B;
+  std::memset(&B, 0, sizeof(B));
+  B.npairs = np;
+  long long off = 0;
+  for (int ph = 0; ph < NPH; ++ph) {
+    B.phase_off[ph] = off;
+    long long* row = &items[(size_t)ph * (np + 1)];
+    row[0] = 0;
+    for (int q = 0; q < np; ++q) {
+      const Snap& x = sn[psnap[q]];
+      const long long tiles = x.z.tiles;
+      const long long k1 = std::min<long long>(std::max<long long>(1, (tiles + 31) / 32), 4096);
+      long long cnt = 1;
+      if (ph == PH_P0) {
+        const long long st_tiles = x.z.sample_stride ? (tiles + x.z.sample_stride - 1) / x.z.sample_stride : 0;
+        cnt = x.z.sample_stride ? std::max<long long>(1, std::min<long long>(st_tiles, (st_tiles + 7) / 8)) : 0;
+      } else if (ph == PH_P1 || ph == PH_P2) {
+        cnt = k1;
+      } else if (ph == PH_R2 || ph == PH_R3 || ph == PH_R4 || ph == PH_R5 || ph == PH_R6) {
+        cnt = std::min<long long>(64, std::max<long long>(1, (long long)(x.z.nv / 262144)));
+      } else if (ph == PH_P3) {
+        cnt = tiles;
+      }
+      row[q + 1] = row[q] + cnt;
+    }
+    off += row[np];
+  }
+  B.phase_off[NPH] = off;
+  // device tables: jobs, pair maps, item prefixes, counters
+  const size_t sz_jobs = sizeof(Job) * count, sz_pairs = sizeof(int) * np, sz_items = sizeof(long long) * items.size(),
+               sz_done = sizeof(u32) * NPH * np;
+  auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+  const size_t o_jobs = 0, o_ps = al(sz_jobs), o_pc = o_ps + al(sz_pairs), o_items = o_pc + al(sz_pairs),
+               o_done = o_items + al(sz_items), o_ticket = o_done + al(sz_done), o_err = o_ticket + 256,
+               total = o_err + 256;
+  char* tab = (char*)c->arena->alloc(total);
+  if (!tab) {
+    cleanup();
+    return fail(ISR_ENOMEM, "batch tables do not fit the HBM budget");
+  }
+  std::vector<char> host(total, 0);
+  for (int i = 0; i < count; ++i) std::memcpy(host.data() + o_jobs + sizeof(Job) * i, &sn[i].j, sizeof(Job));
+  std::memcpy(host.data() + o_ps, psnap.data(), sz_pairs);
+  std::memcpy(host.data() + o_pc, pcomp.data(), sz_pairs);
+  std::memcpy(host.data() + o_items, items.data(), sz_items);
+  B.jobs = (const Job*)(tab + o_jobs);
+  B.pair_snap = (const int*)(tab + o_ps);
+  B.pair_comp = (const int*)(tab + o_pc);
+  B.items = (const long long*)(tab + o_items);
+  B.done = (u32*)(tab + o_done);
+  B.ticket = (unsigned long long*)(tab + o_ticket);
+  B.err = (int*)(tab + o_err);
+  int rc = ISR_OK;
+  int err_host = 0;
+  do {
+    // the fields of the other snapshots must be ready on their own streams
+    for (int i = 1; i < count; ++i) {
+      if (fs[i].stream == fs[0].stream) continue;
+      hipEvent_t e;
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess) {
+        (void)hipEventRecord(e, (hipStream_t)fs[i].stream);
+        (void)hipStreamWaitEvent(s, e, 0);
+        (void)hipEventDestroy(e);
+      }
+    }
+    if (hipMemcpyAsync(tab, host.data(), total, hipMemcpyHostToDevice, s) != hipSuccess) {
+      rc = fail(ISR_EDEVICE, "batch table upload failed");
+      break;
+    }
+    for (int i = 0; i < count && !rc; ++i)
+      if (launch_zero(sn[i].scratch, sn[i].z.zero_bytes, s) != hipSuccess) rc = fail(ISR_EDEVICE, "zero fill failed");
+    if (rc) break;
+    const size_t lds = batch_lds(prec);
+    const int grid = c->num_cu * batch_resident(prec, lds);
+    if (launch_batch(prec, B, grid, lds, s) != hipSuccess) {
+      rc = fail(ISR_EDEVICE, "batch launch failed: %s", hipGetErrorString(hipGetLastError()));
+      break;
+    }
+    for (int i = 0; i < count; ++i)
+      (void)hipMemcpyAsync(sn[i].hs, sn[i].j.st, sizeof(CompState) * fs[i].ncomp, hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(&err_host, B.err, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (hipStreamSynchronize(s) != hipSuccess) {
+      rc = fail(ISR_EDEVICE, "batch failed: %s", hipGetErrorString(hipGetLastError()));
+      break;
+    }
+    if (err_host) rc = fail(ISR_EDEVICE, "batch: a bounded wait expired");
+  } while (0);
+  c->arena->free(tab);
+  if (rc) {
+    cleanup();
+    return rc;
+  }
+  int first = ISR_OK;
+  for (int i = 0; i < count; ++i) {
+    Snap& x = sn[i];
+    const isr_field* f = &fs[i];
+    int flags = 0;
+    bool repair = false;
+    for (int k = 0; k < f->ncomp; ++k) {
+      flags |= x.hs[k].flags;
+      if (f->tol >= 0.0 && x.hs[k].rel > f->tol) repair = true;
+    }
+    int r = status_from_flags(flags);
+    isr_stats* sti = st ? &st[i] : nullptr;
+    if (r == ISR_OK && repair) {
+      // rounding left the error above tol: the single path repairs it
+      c->arena->free(x.scratch);
+      x.scratch = nullptr;
+      c->arena->free(x.b->dev);
+      delete x.b;
+      x.b = nullptr;
+      r = run_compress(c, f, &outs[i], sti);
+    } else if (r == ISR_OK) {
+      isr_blob* b = x.b;
+      isr_stats tmp;
+      std::memset(&tmp, 0, sizeof(tmp));
+      fill_stats(b, x.hs, &tmp);
+      b->status = ISR_OK;
+      const size_t used = 256 + b->bitmap_bytes() + b->ptr_bytes() + b->values_bytes();
+      c->arena->shrink(b->dev, used);
+      b->dev_bytes = (used + 255) & ~size_t(255);
+      tmp.status = ISR_OK;
+      tmp.t_start = t_start;
+      tmp.t_done = now_s();
+      if (sti) *sti = tmp;
+      outs[i] = b;
+      x.b = nullptr;
+    }
+    if (sti) sti->status = r;
+    if (r != ISR_OK && first == ISR_OK) first = r;
+  }
+  cleanup();
+  return first;
+}
+
+// Run one compression to completion on the caller's stream.
+int run_compress(isr_ctx* c, const isr_field* f, isr_blob** out, isr_stats* st) {
+  *out = nullptr;
+  Task t;
+  int rc = task_begin(c, f, (hipStream_t)f->stream, (c->flags & ISR_FLAG_TIMING) && st, &t);
+  if (rc) return rc;
+  for (;;) {
+    if (hipEventSynchronize(t.done) != hipSuccess) {
+      rc = fail(ISR_EDEVICE, "device pipeline failed: %s", hipGetErrorString(hipGetLastError()));
+      task_release(&t);
+      return rc;
+    }
+    rc = task_step(&t, out);
+    if (rc != ISR_PENDING) break;
+  }
+  if (st) *st = t.st;
+  return rc;
 }
 
 }  // namespace isr
@@ -591,6 +862,7 @@ int isr_destroy(isr_ctx* c) {
   c->arena.reset();
   if (c->tables_dev) (void)hipFree(c->tables_dev);
   if (c->st_host) (void)hipHostFree(c->st_host);
+  for (CompState* p : c->host_all) (void)hipHostFree(p);
   delete c;
   return ISR_OK;
 }

@@ -63,32 +63,74 @@ Sizes plan_sizes(const isr_field* f);
 int enqueue_pipeline(isr_ctx* c, const Job& j, const Sizes& z, hipStream_t s, hipEvent_t* ev);
 int run_compress(isr_ctx* c, const isr_field* f, isr_blob** out, isr_stats* st);
 int run_batch(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_stats* st);
+int run_batch_sequential(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_stats* st);
+uint64_t request_footprint(const isr_field* f);
+int ctx_device(const isr_ctx* c);
+int ctx_max_inflight(const isr_ctx* c);
+uint64_t ctx_budget(const isr_ctx* c);
 
-// Request queue behind isr_submit / isr_poll.
+// One compression in flight: its allocations, job, stream and completion event.
+struct Task {
+  isr_ctx* c = nullptr;
+  isr_field f;
+  Sizes z;
+  char* scratch = nullptr;
+  isr_blob* b = nullptr;
+  Job j;
+  hipStream_t s = nullptr;
+  CompState* hs = nullptr;   // pinned copy of the per-component state
+  hipEvent_t done = nullptr; // recorded after the state copy
+  hipEvent_t ev[7] = {};
+  bool timing = false;
+  int iters = 0;
+  float repair_ms = 0.f;
+  double t_start = 0;
+  isr_stats st;
+};
+int task_begin(isr_ctx* c, const isr_field* f, hipStream_t s, bool timing, Task* t);
+int task_step(Task* t, isr_blob** out);
+void task_release(Task* t);
+
+// Continuous batching behind isr_submit / isr_poll.  A scheduler thread admits
+// queued requests while a slot (max_inflight streams) and HBM budget are free,
+// each admitted request runs its whole pipeline on its own stream so the
+// kernels of different requests overlap on the device, and completions are
+// retired (and their memory reused) as soon as their event fires.
 class Scheduler {
  public:
   explicit Scheduler(isr_ctx* c);
   ~Scheduler();
   int submit(const isr_field* f, uint64_t* req);
   int poll(uint64_t req, int wait_ms, isr_blob** out, isr_stats* st);
+  uint64_t admitted_high_water() const { return high_; }
 
  private:
   struct Req {
-    uint64_t id;
+    uint64_t id = 0;
     isr_field f;
-    double t_submit;
+    double t_submit = 0;
+    hipEvent_t ready = nullptr;  // producer stream's state at submit time
     bool done = false;
     int status = 0;
     isr_blob* blob = nullptr;
     isr_stats st;
   };
+  struct Slot {
+    hipStream_t s = nullptr;
+    bool busy = false;
+    uint64_t id = 0;
+    Task t;
+  };
   void loop();
+  bool admit_locked();
   isr_ctx* ctx_;
   std::mutex mu_;
   std::condition_variable cv_, done_cv_;
   std::deque<uint64_t> queue_;
   std::map<uint64_t, Req> reqs_;
+  std::vector<Slot> slots_;
   uint64_t next_id_ = 1;
+  uint64_t high_ = 0;
   bool stop_ = false;
   std::thread worker_;
 };

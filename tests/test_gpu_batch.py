@@ -1,0 +1,50 @@
+"""One persistent launch over a batch of snapshots (orders 5, 7, 9, uneven
+sizes): every result must equal the same snapshot compressed alone, bit for
+bit (all global sums are exact, so the queue order cannot change them), and
+the FP64 members must equal the oracle."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _batch(rng, count, emin, emax, seed0):
+    out = []
+    for i in range(count):
+        N = int(rng.choice([5, 7, 9]))
+        E = int(round(np.exp(rng.uniform(np.log(emin), np.log(emax)))))
+        out.append((N, E, torch.from_numpy(synth.field(E, N, seed=seed0 + i)).cuda()))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_batch_equals_alone(isr_ctx, prec):
+    rng = np.random.default_rng(11)
+    snaps = _batch(rng, 10, 30, 5000, 700)
+    snaps.append((7, 4096, torch.from_numpy(synth.field(4096, 7, seed=799)).cuda()))  # sampled window
+    torch.cuda.synchronize()
+    print(f"[case] batch prec={prec} sizes={[(N, E) for N, E, _ in snaps]}", flush=True)
+    blobs = isr_ctx.compress_batch([(u, N, 1e-3) for N, E, u in snaps], prec)
+    for (N, E, u), b in zip(snaps, blobs):
+        assert b.status == 0
+        alone = isr_ctx.compress(u, N, 1e-3, prec)
+        assert b.to_bytes() == alone.to_bytes(), (N, E)
+
+
+def test_batch_fp64_matches_oracle(isr_ctx):
+    rng = np.random.default_rng(12)
+    snaps = _batch(rng, 6, 20, 400, 800)
+    torch.cuda.synchronize()
+    blobs = isr_ctx.compress_batch([(u, N, 1e-3) for N, E, u in snaps], "fp64")
+    for (N, E, u), b in zip(snaps, blobs):
+        arr = b.arrays()
+        ref = oracle.compress(u.cpu().numpy(), N, 1e-3)
+        for c, rc in enumerate(ref.comps):
+            assert arr.comps[c]["tau"] == rc.tau and arr.comps[c]["kept"] == rc.kept
+            assert np.array_equal(arr.bitmap[c], rc.bitmap)
+            assert np.array_equal(arr.values[c].view(np.uint64), rc.values.view(np.uint64))

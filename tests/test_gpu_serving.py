@@ -1,0 +1,91 @@
+"""Continuous batching behind isr_submit / isr_poll, on the GPU.
+
+Requests of different sizes and orders (element windows of device-resident
+pools, FP32 MFMA path, tol 1e-3) are submitted back to back; the scheduler
+admits them while stream slots and HBM budget are free and their pipelines
+overlap on the device.  Each result must equal the same request compressed
+alone (bit-identical: every global sum is exact, so scheduling cannot change
+it), requests must actually overlap, and a small budget must bound what is
+admitted without deadlock.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _pools(orders, n_elem, seed0=500):
+    return {N: torch.from_numpy(synth.field(n_elem, N, seed=seed0 + N)).cuda() for N in orders}
+
+
+def _requests(pools, rng, count, emax):
+    reqs = []
+    for _ in range(count):
+        N = int(rng.choice(sorted(pools)))
+        E = int(np.clip(round(np.exp(rng.normal(np.log(600), 0.8))), 40, emax))
+        off = int(rng.integers(0, pools[N].shape[1] - E + 1))
+        reqs.append((N, off, E))
+    return reqs
+
+
+def test_mix_equals_alone_and_overlaps():
+    from paper_2407_20731_amd import isr
+    pools = _pools((5, 7, 9), 3000)
+    rng = np.random.default_rng(7)
+    reqs = _requests(pools, rng, 24, 2500)
+    with isr.Context(device=0, max_inflight=6) as ctx:
+        torch.cuda.synchronize()
+        ids = [ctx.submit(pools[N][:, off:off + E], N, 1e-3, "fp32") for (N, off, E) in reqs]
+        mixed = [ctx.poll(r, wait_ms=-1) for r in ids]
+        alone = [ctx.compress(pools[N][:, off:off + E], N, 1e-3, "fp32") for (N, off, E) in reqs]
+        torch.cuda.synchronize()
+        for (N, off, E), m, a in zip(reqs, mixed, alone):
+            assert m.status == isr.OK and a.status == isr.OK
+            assert m.to_bytes() == a.to_bytes(), (N, off, E)
+            assert max(m.stats["rel_err"]) <= 1e-3
+        spans = sorted((m.stats["t_start"], m.stats["t_done"]) for m in mixed)
+        overlaps = sum(1 for k in range(1, len(spans)) if spans[k][0] < spans[k - 1][1])
+        print(f"[serving] {len(spans)} requests, {overlaps} started before the previous one finished", flush=True)
+        assert overlaps >= 3
+
+
+def test_budget_bounds_admission():
+    from paper_2407_20731_amd import isr
+    pools = _pools((7,), 4000, seed0=600)
+    u = pools[7]
+    # the whole pool (4000 elements) needs ~125 MB of scratch + blob, a window
+    # of 1500 elements ~47 MB: at most two windows fit at once
+    with isr.Context(device=0, max_inflight=8, budget_bytes=100 << 20) as ctx:
+        # one request alone above the budget is refused at submit
+        with pytest.raises(isr.IsrError) as e:
+            ctx.submit(u, 7, 1e-3, "fp32")
+        assert e.value.code == isr.ENOMEM
+        torch.cuda.synchronize()
+        reqs = [(o, 1500) for o in (0, 500, 1000, 1500, 2000, 2500)]
+        ids = [ctx.submit(u[:, o:o + E], 7, 1e-3, "fp32") for (o, E) in reqs]
+        outs = [ctx.poll(r, wait_ms=-1) for r in ids]
+        for (o, E), b in zip(reqs, outs):
+            assert b.status == isr.OK
+            ref = ctx.compress(u[:, o:o + E], 7, 1e-3, "fp32")
+            assert b.to_bytes() == ref.to_bytes()
+
+
+def test_poll_unknown_and_pending():
+    from paper_2407_20731_amd import isr
+    with isr.Context(device=0) as ctx:
+        with pytest.raises(isr.IsrError) as e:
+            ctx.poll(987654321)
+        assert e.value.code == isr.ENOTFOUND
+        u = torch.from_numpy(synth.field(2000, 9, seed=9)).cuda()
+        torch.cuda.synchronize()
+        r = ctx.submit(u, 9, 1e-3, "bf16")
+        b = None
+        for _ in range(10000):
+            b = ctx.poll(r, wait_ms=5)
+            if b is not None:
+                break
+        assert b is not None and b.status == isr.OK
