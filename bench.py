@@ -1,13 +1,23 @@
 """Benchmark: field GB/s compressed at relative L2 error <= 1e-3 on one MI355X.
 
-Workload: one snapshot of 65,536 hexahedral spectral elements, order N = 7
-(8x8x8 GLL points), 3 FP64 velocity components (805 MB), from the seeded
-Fourier-mode generator (64 modes, k^-5/3 spectrum, 1e-6 noise), tol 1e-3.
-A step is one full compression (every phase: histogram pass, threshold
-select, candidate pass, refinement, compaction + verification pass,
-finalize) with the field already resident in HBM.  Output: ONE JSON line.
+Headline workload: one snapshot of 65,536 hexahedral spectral elements,
+order N = 7 (8x8x8 GLL points), 3 FP64 velocity components (805 MB) from the
+seeded Fourier-mode generator (64 modes, k^-5/3 spectrum, 1e-6 noise), tol
+1e-3, compressed with the mixed-precision path (BF16-split or FP32 MFMA
+transforms, FP64 norm / threshold / check).  A step is one full compression
+(every phase) with the field resident in HBM.  The same snapshot is also
+timed on the plain FP64 path (speedup reported), and two more sections run:
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32|bf16]
+  batch    32 snapshots, element counts log-uniform 4k-200k, N in {5,7,9},
+           3 FP64 components, tol 1e-3, one persistent launch
+  serving  open-loop Poisson arrivals, element counts lognormal (median 20k,
+           sigma 1, clipped 1k-500k), N in {5,7,9}, FP32 MFMA path, tol 1e-3,
+           64 GB admission budget: p50 / p99 latency and GB/s
+
+Output: ONE JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision auto|fp64|fp32|bf16]
+                    [--no-cpu] [--no-batch] [--no-serving]
 """
 
 from __future__ import annotations
@@ -29,6 +39,11 @@ FP64_NOFMA_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
 
 E_BENCH, ORDER, NCOMP, TOL, SEED = 65536, 7, 3, 1e-3, 2
 CPU_SAMPLE_ELEMS = 16384
+DTYPES = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def flops_per_value(phase: str, n: int) -> int:
@@ -43,8 +58,6 @@ def flops_per_value(phase: str, n: int) -> int:
 
 
 def cpu_baseline() -> dict:
-    import numpy as np  # noqa: F401
-
     import oracle
     import synth
 
@@ -57,84 +70,215 @@ def cpu_baseline() -> dict:
                       f"tol 1e-3), full oracle pipeline, single-threaded NumPy, {dt:.1f} s"}
 
 
+def time_single(ctx, u, prec, steps, warmup, stream):
+    import numpy as np
+    import torch
+
+    for _ in range(warmup):
+        ctx.compress(u, ORDER, TOL, prec, stream=stream).free()
+    torch.cuda.synchronize()
+    phases, rels, kept, status = {}, [], [], set()
+    blob_bytes = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b = ctx.compress(u, ORDER, TOL, prec, stream=stream)
+        for k, v in b.stats["phase_ms"].items():
+            phases.setdefault(k, []).append(v)
+        rels.append(max(b.stats["rel_err"]))
+        kept.append(sum(b.stats["kept"]))
+        status.add(b.status)
+        blob_bytes = b.stats["blob_bytes"]
+        b.free()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    return {"ms": ms, "phase_ms": {k: float(np.mean(v)) for k, v in phases.items()}, "max_rel": max(rels),
+            "kept": kept[-1], "status": sorted(status), "blob_bytes": blob_bytes}
+
+
+def pools(orders, n_elem):
+    import synth
+    return {N: synth.field_torch(n_elem, N, ncomp=NCOMP, seed=900 + N, device="cuda") for N in orders}
+
+
+def run_batch(ctx, pool, prec):
+    """Config 4: 32 snapshots, E log-uniform 4k-200k, N uniform in {5,7,9}."""
+    import numpy as np
+    import torch
+
+    rng = np.random.default_rng(4)
+    fields, nbytes = [], 0
+    for _ in range(32):
+        N = int(rng.choice([5, 7, 9]))
+        E = int(round(math.exp(rng.uniform(math.log(4096), math.log(200000)))))
+        off = int(rng.integers(0, pool[N].shape[1] - E + 1))
+        fields.append((pool[N][:, off:off + E], N, TOL))
+        nbytes += NCOMP * E * (N + 1) ** 3 * 8
+    ctx.compress_batch(fields[:4], prec)  # warm up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    blobs = ctx.compress_batch(fields, prec)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ok = all(b.status == 0 for b in blobs)
+    rel = max(max(b.stats["rel_err"]) for b in blobs)
+    for b in blobs:
+        b.free()
+    return {"snapshots": 32, "total_GB": nbytes / 1e9, "seconds": dt, "GBps": nbytes / dt / 1e9,
+            "precision": prec, "all_ok": ok, "max_rel_err": rel}
+
+
+def run_serving(pool, prec, budget, n_req, rate_frac):
+    """Config 5: Poisson arrivals, E lognormal (median 20k, sigma 1, clip
+    1k-500k), N uniform in {5,7,9}, continuous batching under an HBM budget."""
+    import numpy as np
+    import torch
+
+    from paper_2407_20731_amd import isr
+
+    rng = np.random.default_rng(5)
+    reqs = []
+    for _ in range(n_req):
+        N = int(rng.choice([5, 7, 9]))
+        E = int(np.clip(round(math.exp(rng.normal(math.log(20000), 1.0))), 1000, 500000))
+        off = int(rng.integers(0, pool[N].shape[1] - E + 1))
+        reqs.append((N, off, E))
+    with isr.Context(device=0, budget_bytes=budget, max_inflight=8) as ctx:
+        def submit(r):
+            N, off, E = r
+            return ctx.submit(pool[N][:, off:off + E], N, TOL, prec)
+        # saturated (closed-loop) rate on the first 48 requests
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ids = [submit(r) for r in reqs[:48]]
+        for i in ids:
+            ctx.poll(i, wait_ms=-1).free()
+        sat = 48 / (time.perf_counter() - t0)
+        rate = rate_frac * sat
+        # open loop: arrivals at exponential gaps, polled as they finish
+        gaps = rng.exponential(1.0 / rate, size=n_req)
+        arrive = np.cumsum(gaps)
+        pending, lat, nbytes = {}, [], 0
+        t0 = time.perf_counter()
+        k = 0
+        while k < n_req or pending:
+            now = time.perf_counter() - t0
+            while k < n_req and arrive[k] <= now:
+                pending[submit(reqs[k])] = reqs[k]
+                k += 1
+            for rid in list(pending):
+                b = ctx.poll(rid, wait_ms=0)
+                if b is not None:
+                    N, off, E = pending.pop(rid)
+                    lat.append((b.stats["t_done"] - b.stats["t_submit"]) * 1e3)
+                    nbytes += NCOMP * E * (N + 1) ** 3 * 8
+                    b.free()
+            time.sleep(0.0002)
+        wall = time.perf_counter() - t0
+    lat = np.array(lat)
+    return {"requests": n_req, "rate_per_s": rate, "saturated_rate_per_s": sat, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "GBps": nbytes / wall / 1e9, "precision": prec,
+            "budget_GB": budget / 2 ** 30}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32", "bf16"))
+    ap.add_argument("--precision", default="auto", choices=("auto", "fp64", "fp32", "bf16"))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path is single-GPU "
               "by design; see the sharding notes in DESIGN.md)", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     import synth
     from paper_2407_20731_amd import isr
 
     torch.cuda.set_device(0)
-    print(f"[bench] generating {E_BENCH} elements, N={ORDER}, {NCOMP} components", file=sys.stderr, flush=True)
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": src.numel() * 4, "copies": 3}), flush=True)
+        return 0
+    log(f"generating {E_BENCH} elements, N={ORDER}, {NCOMP} components")
     u = torch.from_numpy(synth.field(E_BENCH, ORDER, ncomp=NCOMP, seed=SEED)).cuda()
     torch.cuda.synchronize()
     n = ORDER + 1
     nvals = NCOMP * E_BENCH * n ** 3
-    ctx = isr.Context(device=0, flags=isr.FLAG_TIMING)
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        b = ctx.compress(u, ORDER, TOL, args.precision, stream=stream)
-        b.free()
-    print("[bench] warmup done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    phases = {k: [] for k in isr.PHASES}
-    rels, kept, status = [], [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        b = ctx.compress(u, ORDER, TOL, args.precision, stream=stream)
-        for k, v in b.stats["phase_ms"].items():
-            phases[k].append(v)
-        rels.append(max(b.stats["rel_err"]))
-        kept.append(sum(b.stats["kept"]))
-        status.append(b.status)
-        blob_bytes = b.stats["blob_bytes"]
-        b.free()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms = dt / args.steps * 1e3
-    gbs = (nvals * 8) / (ms / 1e3) / 1e9
-    avg = {k: float(np.mean(v)) for k, v in phases.items() if v}
+    ctx = isr.Context(device=0, flags=isr.FLAG_TIMING)
+    results = {}
+    precs = ["bf16", "fp32", "fp64"] if args.precision == "auto" else [args.precision]
+    for p in precs:
+        steps = args.steps if p != "fp64" or args.precision == "fp64" else max(2, args.steps // 3)
+        results[p] = time_single(ctx, u, p, steps, args.warmup, stream)
+        log(f"{p}: {results[p]['ms']:.3f} ms/step, phases {results[p]['phase_ms']}")
+    if args.precision == "auto":
+        ok = [p for p in ("bf16", "fp32") if results[p]["status"] == [0] and results[p]["max_rel"] <= TOL]
+        head = min(ok, key=lambda p: results[p]["ms"]) if ok else "fp64"
+    else:
+        head = args.precision
+    r = results[head]
+    gbs = (nvals * 8) / (r["ms"] / 1e3) / 1e9
+    avg = r["phase_ms"]
     dom = max(("pass1", "pass2", "pass3"), key=lambda k: avg.get(k, 0.0))
-    if args.precision == "fp64":
+    if head == "fp64":
         flops = flops_per_value(dom, n) * nvals
         achieved = flops / (avg[dom] / 1e3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": FP64_NOFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_NOFMA_PEAK_TFLOPS, "traffic": None, "kernel": dom,
-                "kernel_ms": avg[dom]}
+                "frac": achieved / FP64_NOFMA_PEAK_TFLOPS, "traffic": None, "kernel": dom, "kernel_ms": avg[dom]}
     else:
-        byts = nvals * 8 + (blob_bytes if dom == "pass3" else 0)
+        byts = nvals * 8 + (r["blob_bytes"] if dom == "pass3" else 0)
         achieved = byts / (avg[dom] / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom, "kernel_ms": avg[dom]}
-    ctx.close()
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom, "kernel_ms": avg[dom],
+                "algorithmic_bytes_per_launch": byts}
+    # whole-path algorithmic traffic: two field reads plus the blob, per step
+    algo = 2 * nvals * 8 + r["blob_bytes"]
     out = {
         "metric": METRIC, "value": gbs, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[args.precision],
-        "data": "synthetic",
+        "warmup": args.warmup, "ms_per_step": r["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPES[head], "data": "synthetic",
         "config": {"workload": "single snapshot: 65,536 hex elements, N=7 (8^3 GLL points), 3 FP64 velocity "
                                "components (805 MB), Fourier-mode generator seed 2, tol 1e-3",
-                   "n_elem": E_BENCH, "order": ORDER, "ncomp": NCOMP, "tol": TOL, "precision": args.precision},
+                   "n_elem": E_BENCH, "order": ORDER, "ncomp": NCOMP, "tol": TOL, "precision": head},
         "roofline": roof,
+        "path_hbm_frac": algo / (r["ms"] / 1e3) / 1e9 / HBM_PEAK_GBS,
         "phase_ms": avg,
-        "max_rel_err": max(rels), "kept_values": kept[-1], "kept_fraction": kept[-1] / nvals,
-        "status": sorted(set(status)),
-        "blob_bytes": blob_bytes, "cr": (nvals * 8 - blob_bytes) / (nvals * 8),
+        "max_rel_err": r["max_rel"], "kept_fraction": r["kept"] / nvals, "status": r["status"],
+        "blob_bytes": r["blob_bytes"], "cr": (nvals * 8 - r["blob_bytes"]) / (nvals * 8),
+        "by_precision": {p: {"GBps": (nvals * 8) / (v["ms"] / 1e3) / 1e9, "ms": v["ms"], "max_rel_err": v["max_rel"],
+                             "kept": v["kept"], "status": v["status"]} for p, v in results.items()},
     }
+    if "fp64" in results and head != "fp64":
+        out["speedup_vs_fp64"] = results["fp64"]["ms"] / r["ms"]
+    ctx.close()
+    if not (args.no_batch and args.no_serving):
+        log("generating element pools on the device (500k elements per order)")
+        pool = pools((5, 7, 9), 500000)
+        torch.cuda.synchronize()
+        if not args.no_batch:
+            with isr.Context(device=0, budget_bytes=128 << 30) as bctx:
+                out["batch"] = run_batch(bctx, pool, head)
+                log(f"batch: {out['batch']}")
+        if not args.no_serving:
+            out["serving"] = run_serving(pool, "fp32", 64 << 30, args.serving_requests, 0.7)
+            log(f"serving: {out['serving']}")
+        del pool
     if not args.no_cpu:
-        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
     return 0

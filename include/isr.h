@@ -133,11 +133,15 @@ typedef struct {
   float phase_ms[ISR_NPHASE];    /* ISR_FLAG_TIMING: device ms per phase:
                                     0 norm+histogram pass, 1 threshold select,
                                     2 candidate pass, 3 refine, 4 compact+verify
-                                    pass, 5 finalize, 6 repair total, 7 unused */
+                                    pass, 5 finalize, 6 repair total, 7 an
+                                    abandoned streaming attempt (see path) */
   int32_t repair_iters;
   int32_t status;
   int32_t precision;
-  int32_t reserved;
+  int32_t path;                  /* 1: streaming path (orders 1..7, threshold
+                                    inside the sampled window); 0: general
+                                    pipeline (other orders, or the window
+                                    missed and the request was rerun) */
 } isr_stats;
 
 /* Create a context on cfg->device (cfg may be NULL: device 0, defaults).

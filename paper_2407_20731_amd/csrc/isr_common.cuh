@@ -129,14 +129,20 @@ DEV void chunk32(const HistBin* H, u64& lo, u64& hi, u64& cnt, int& base) {
   base = 32 * l > 1 ? 32 * l : 1;
   u128 acc = 0;
   u64 c = 0;
+  // all 32 bins are loaded before any is used (independent loads in flight)
+  HistBin hb[32];
+#pragma unroll
   for (int k = 0; k < 32; ++k) {
-    int b = 32 * l + k;
-    if (b >= HBINS - 1) break;
-    HistBin h = H[b];
-    if (h.cnt == 0) continue;
+    const int b = 32 * l + k;
+    hb[k] = b < HBINS - 1 ? H[b] : HistBin{0ull, 0ull, 0ull};
+  }
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    const int b = 32 * l + k;
+    if (hb[k].cnt == 0) continue;
     int sh = (b > 1 ? b : 1) - base;
-    acc += bin_sum(h) << sh;
-    c += h.cnt;
+    acc += bin_sum(hb[k]) << sh;
+    c += hb[k].cnt;
   }
   lo = (u64)acc;
   hi = (u64)(acc >> 64);
@@ -230,6 +236,13 @@ DEV void lh_flush(LdsHist& h, HistBin* g, int tid, int nthr) {
 }
 
 // ---- candidate lists -------------------------------------------------------------
+// Per component: list 0 (capacity list_cap) then lists 1 and 2 (list_cap / 2
+// each; they only hold the members of one refinement sub-bin).
+DEV u64* list_ptr(const Job& j, int comp, int k) {
+  return j.lists + (size_t)comp * 2 * j.list_cap + (k == 0 ? 0 : j.list_cap + (size_t)(k - 1) * (j.list_cap / 2));
+}
+DEV u64 list_capk(const Job& j, int k) { return k == 0 ? j.list_cap : j.list_cap / 2; }
+
 // Wave-aggregated append; the counter may run past cap (then ST_LIST is set
 // and readers clamp to cap).
 DEV void list_append(u64* list, u64* count, u64 cap, bool m, u64 key, int* flag) {
@@ -315,6 +328,9 @@ template <int n>
 DEV void contract64(const double* __restrict__ M, const double (&x)[n], double (&y)[n]) {
 #pragma unroll
   for (int a = 0; a < n; ++a) {
+    // keep the row loads of M here (LDS broadcast reads) instead of letting
+    // the compiler hold all n*n entries in VGPRs across stages
+    asm volatile("" ::: "memory");
     double acc = M[a * n] * x[0];
 #pragma unroll
     for (int b = 1; b < n; ++b) acc = acc + M[a * n + b] * x[b];

@@ -53,7 +53,7 @@ struct alignas(256) CompState {
   u64 cur_count;      // members of the current bin / sub-bin
   u64 r_lo, r_hi;     // 128-bit slack, in significand units of the boundary bin
   u64 w_lo, w_hi;     // 128-bit significand sum dropped inside the boundary bin
-  u64 list_count[2];  // candidate list fill levels
+  u64 list_count[3];  // candidate list fill levels
   int32_t bstar;      // boundary exponent bin, -1 when tau is +inf or 0
   int32_t level;      // last level decided
   int32_t resolved;   // tau final
@@ -62,7 +62,13 @@ struct alignas(256) CompState {
   int32_t win_hi;     //   by pass 1 (empty when win_lo >= win_hi)
   int32_t need_pass2; // boundary bin outside the window: run the candidate pass
   int32_t list0_exact;  // list 0 holds exactly the boundary bin's energies
-  int32_t pad[3];
+  // streaming path (isr_engine.cuh): the energy histogram holds exact sums
+  // only inside the window, everything below it as one exact total
+  int32_t win_mode;
+  int32_t xm_norm;    // log2 of the bound on norm terms used by the extraction sums
+  int32_t xm_err;     // same for the error terms
+  int32_t samp_maxe;  // largest biased exponent of a sampled norm term
+  double samp_u2;     // sampled norm terms (rounded sum, only to place the window)
 };
 
 enum : int32_t {
@@ -70,6 +76,8 @@ enum : int32_t {
   ST_OVERFLOW = 2,    // an energy or norm term overflowed FP64
   ST_SPIN = 4,        // a bounded wait expired (should never happen)
   ST_LIST = 8,        // a candidate list overflowed its capacity
+  ST_MISS = 16,       // streaming path: tau outside the sampled window (the
+                      // general pipeline runs instead; not an error)
 };
 
 struct DevTables {
@@ -103,8 +111,18 @@ struct Job {
   HistBin* histNs;     // [ncomp][HBINS]  norm terms of the sampled tiles
   long long sample_stride;  // every sample_stride-th tile is sampled; 0 = no sample pass
   CompState* st;       // [ncomp]
-  u64* lists;          // [ncomp][2][list_cap]
+  u64* lists;          // [ncomp][3][list_cap]
   u64 list_cap;
+  // streaming path
+  u32* lidx;           // [ncomp][list_cap] element of each list-0 entry
+  u32* cnt;            // [ncomp][n_elem] kept coefficients per element
+  long long* slotsA;   // [ncomp][gA][8] per-workgroup exact partial sums
+  long long* slotsB;   // [ncomp][gB][4]
+  u32* done;           // [16][8] finished-workgroup counters
+  u64* chunk;          // [ncomp][nchunk] element-offset scan: chunk sums, then offsets
+  long long nchunk;
+  int gA, gB;          // workgroups per component of the two streaming passes
+  int xh;              // extraction headroom (log2 of twice the terms per lane)
   u64* lookback;       // [ncomp][tiles]
   u32* ticket;         // [4]
   // blob (device)
@@ -165,6 +183,23 @@ hipError_t launch_select1(const Job& j, int sample, hipStream_t s);
 hipError_t launch_refine(const Job& j, int level, int grid_x, hipStream_t s);
 hipError_t launch_select(const Job& j, int level, hipStream_t s);
 hipError_t launch_finalize(const Job& j, hipStream_t s);
+hipError_t launch_refsel(const Job& j, int level, int grid_x, hipStream_t s);
+
+// Streaming path (isr_engine.cuh) for orders 1..7.
+enum FastKind { F_SAMPLE = 0, F_PASSA = 1, F_PASSB = 2 };
+enum DoneSlot { D_SAMPLE = 0, D_GATHER = 1, D_COUNT = 2, D_PASSB = 3, D_REFSEL = 4 };  // D_REFSEL + level
+constexpr int FAST_MAX_ORDER = 7;
+constexpr int FAST_GMAX = 2048;  // workgroups per component of a streaming pass
+hipError_t launch_fast(int kind, int precision, const Job& j, int grid_x, hipStream_t s);
+int resident_fast(int kind, int precision, int order);
+hipError_t launch_fast_fp64(int kind, const Job& j, int grid_x, hipStream_t s);
+hipError_t launch_fast_fp32(int kind, const Job& j, int grid_x, hipStream_t s);
+hipError_t launch_fast_bf16(int kind, const Job& j, int grid_x, hipStream_t s);
+int resident_fast_fp64(int kind, int order);
+int resident_fast_fp32(int kind, int order);
+int resident_fast_bf16(int kind, int order);
+hipError_t launch_gather(const Job& j, int grid_x, hipStream_t s);
+hipError_t launch_count(const Job& j, int grid_x, hipStream_t s);
 
 // Host tables (isr_tables.cpp): correctly rounded FP64 values.
 struct HostTables {

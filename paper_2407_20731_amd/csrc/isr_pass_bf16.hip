@@ -1,6 +1,7 @@
 // Streaming passes and the persistent batch kernel instantiated for the
 // BF16 transform path.
 #include "isr_batch.cuh"
+#include "isr_engine.cuh"
 #include "isr_passes.cuh"
 
 namespace isr {
@@ -18,5 +19,11 @@ hipError_t launch_batch_bf16(const BatchCtl& B, int grid, size_t lds, hipStream_
 size_t batch_lds_bf16() { return batch_lds_prec<P_BF16>(); }
 
 int batch_resident_bf16(size_t lds) { return batch_resident_prec<P_BF16>(lds); }
+
+hipError_t launch_fast_bf16(int kind, const Job& j, int gx, hipStream_t s) {
+  return launch_fast_prec<P_BF16>(kind, j, gx, s);
+}
+
+int resident_fast_bf16(int kind, int order) { return resident_fast_prec<P_BF16>(kind, order); }
 
 }  // namespace isr

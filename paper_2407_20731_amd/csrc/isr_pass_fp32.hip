@@ -1,6 +1,7 @@
 // Streaming passes and the persistent batch kernel instantiated for the
 // FP32 transform path.
 #include "isr_batch.cuh"
+#include "isr_engine.cuh"
 #include "isr_passes.cuh"
 
 namespace isr {
@@ -18,5 +19,11 @@ hipError_t launch_batch_fp32(const BatchCtl& B, int grid, size_t lds, hipStream_
 size_t batch_lds_fp32() { return batch_lds_prec<P_FP32>(); }
 
 int batch_resident_fp32(size_t lds) { return batch_resident_prec<P_FP32>(lds); }
+
+hipError_t launch_fast_fp32(int kind, const Job& j, int gx, hipStream_t s) {
+  return launch_fast_prec<P_FP32>(kind, j, gx, s);
+}
+
+int resident_fast_fp32(int kind, int order) { return resident_fast_prec<P_FP32>(kind, order); }
 
 }  // namespace isr

@@ -319,7 +319,7 @@ template <int N, int PREC>
 struct Pass1Lds {
   typedef Shape<N> S;
   typedef typename XfSel<N, PREC>::type X;
-  static constexpr int CB1 = S::TILE + 512;  // room for one whole tile above the flush mark
+  static constexpr int CB1 = 768;  // flushed whenever fewer than 256 slots (one row of appends) remain
   double su[S::TILE];
   typename X::work_t sw_buf[PREC == P_FP64 ? 1 : S::TILE];
   LdsHist hN, hE;
@@ -348,7 +348,7 @@ DEV void pass1_body(const Job& j, int comp, long long t0, long long tstride, int
   HistBin* gE = (sample ? j.histEs : j.histE) + (size_t)comp * HBINS;
   const int wlo = sample ? 0 : st->win_lo, whi = sample ? 0 : st->win_hi;  // [wlo, whi)
   const bool capture = wlo < whi;
-  u64* list = j.lists + ((size_t)comp * 2 + 0) * j.list_cap;
+  u64* list = list_ptr(j, comp, 0);
   typename X::work_t* sw = INPLACE ? (typename X::work_t*)L.su : L.sw_buf;
   __syncthreads();
   lh_init(L.hN, tid, T);
@@ -418,15 +418,19 @@ DEV void pass1_body(const Job& j, int comp, long long t0, long long tstride, int
       for (int r = 0; r < n; ++r) lh_insert(L.hE, gE, en[r]);
     }
     if (capture) {
+      static_assert(T <= 256, "one row of appends adds at most 256 keys");
 #pragma unroll
       for (int r = 0; r < n; ++r) {
         const u64 key = act ? dbits(en[r]) : 0ull;
         const int ex = bits_exp(key);
         cbuf_put(L.cbuf, &L.ncb, act && ex >= wlo && ex < whi, key);
+        __syncthreads();
+        const bool full = L.ncb > (u32)(CB1 - 256);
+        // every thread has read the fill level before the next row appends
+        // (else waves could disagree on the flush and meet at different barriers)
+        __syncthreads();
+        if (full) cbuf_flush(L.cbuf, &L.ncb, &L.gbase_s, list, &st->list_count[0], j.list_cap, &st->flags, tid, T);
       }
-      __syncthreads();
-      if (L.ncb > (u32)(CB1 - S::TILE))
-        cbuf_flush(L.cbuf, &L.ncb, &L.gbase_s, list, &st->list_count[0], j.list_cap, &st->flags, tid, T);
     }
   }
   __syncthreads();
@@ -468,7 +472,7 @@ DEV void pass2_body(const Job& j, int comp, long long t0, long long tstride, Pas
   CompState* st = j.st + comp;
   if (st->resolved || !st->need_pass2) return;
   const u64 prefix = st->key_prefix, mask = st->key_mask;
-  u64* list = j.lists + ((size_t)comp * 2 + 0) * j.list_cap;
+  u64* list = list_ptr(j, comp, 0);
   const int el = tid / n2, a = (tid % n2) / n, b = tid % n;
   const long long E = j.n_elem;
   const long long tiles = (E + EPI - 1) / EPI;
@@ -585,9 +589,13 @@ DEV void pass3_tile(const Job& j, int comp, long long t, Pass3Lds<N, PREC>& L,
   }
   __syncthreads();
   u64* lb = j.lookback + (size_t)comp * tiles;
-  if (tid < 64) lookback_publish(lb, t, L.cntl, ne, &L.excl_s);
-  // inverse transform of the kept set and exact error terms (independent of
-  // the prefix, so the look-back has time to settle meanwhile)
+  // publish the aggregate and resolve the prefix at once, so that inclusive
+  // prefixes follow closely behind the tiles being claimed and look-backs
+  // stay short
+  if (tid < 64) {
+    lookback_publish(lb, t, L.cntl, ne, &L.excl_s);
+    lookback_wait(lb, t, L.cntl, ne, &j.st[comp].flags, &L.excl_s);
+  }
   double et[n];
   {
     double cm[n], ut[n];
@@ -618,7 +626,6 @@ DEV void pass3_tile(const Job& j, int comp, long long t, Pass3Lds<N, PREC>& L,
 #pragma unroll
     for (int i = 0; i < n; ++i) lh_insert(L.hR, j.histR + (size_t)comp * HBINS, et[i]);
   }
-  if (tid < 64) lookback_wait(lb, t, L.cntl, ne, &j.st[comp].flags, &L.excl_s);
   __syncthreads();
   const u64 ex = L.excl_s;
   u64* gbm = j.bitmap + ((size_t)comp * E + e0) * W;

@@ -67,23 +67,23 @@ void Arena::release() {
   used_ = 0;
 }
 
-void* Arena::alloc(size_t bytes) {
+void* Arena::alloc(size_t bytes, bool high) {
   std::lock_guard<std::mutex> g(mu_);
   bytes = (bytes + 255) & ~size_t(255);
   if (bytes == 0) bytes = 256;
-  // best fit over free ranges
+  // low: first fitting range in address order; high: the last one
   int best_c = -1;
-  size_t best_off = 0, best_sz = ~size_t(0);
+  size_t best_off = 0, best_sz = 0;
   for (size_t ci = 0; ci < chunks_.size(); ++ci)
     for (auto& fr : chunks_[ci].free)
-      if (fr.second >= bytes && fr.second < best_sz) {
+      if (fr.second >= bytes && (best_c < 0 || high)) {
         best_c = (int)ci;
         best_off = fr.first;
         best_sz = fr.second;
       }
   if (best_c < 0) {
-    size_t want = std::max(bytes, (size_t)(256ull << 20));
-    if (held_ + want > budget_) want = bytes;
+    // a new chunk: 256 MB, or what is left of the budget, or at least `bytes`
+    size_t want = std::max(bytes, std::min((size_t)(256ull << 20), (size_t)(budget_ > held_ ? budget_ - held_ : 0)));
     if (held_ + want > budget_) return nullptr;
     void* p = nullptr;
     if (hipMalloc(&p, want) != hipSuccess) {
@@ -102,8 +102,14 @@ void* Arena::alloc(size_t bytes) {
   }
   Chunk& c = chunks_[best_c];
   c.free.erase(best_off);
-  if (best_sz > bytes) c.free[best_off + bytes] = best_sz - bytes;
-  char* p = c.base + best_off;
+  size_t at = best_off;
+  if (high) {
+    at = best_off + best_sz - bytes;
+    if (best_sz > bytes) c.free[best_off] = best_sz - bytes;
+  } else if (best_sz > bytes) {
+    c.free[best_off + bytes] = best_sz - bytes;
+  }
+  char* p = c.base + at;
   live_[p] = {best_c, bytes};
   used_ += bytes;
   high_ = std::max(high_, used_);
@@ -293,9 +299,20 @@ Sizes plan_sizes(const isr_field* f) {
   z.off_st = take((size_t)nc * sizeof(CompState));
   z.off_ticket = take(256);
   z.off_lookback = take((size_t)nc * z.tiles * 8);
+  z.off_done = take(16 * 8 * sizeof(u32));
   z.zero_bytes = o;
   z.list_cap = z.nv;
-  z.off_lists = take((size_t)nc * 2 * z.list_cap * 8);
+  z.off_lists = take((size_t)nc * 2 * z.list_cap * 8);  // list 0, then lists 1 and 2 at half size
+  z.fast = f->order <= FAST_MAX_ORDER;
+  if (z.fast) {
+    const long long epw = 64 / (n * n), ftiles = (f->n_elem + epw - 1) / epw;
+    z.sample_stride = std::max<long long>(1, ftiles / 1024);  // about 1024 sampled tiles
+    z.off_lidx = take((size_t)nc * z.list_cap * 4);
+    z.off_cnt = take((size_t)nc * f->n_elem * 4);
+    z.off_slotsA = take((size_t)nc * FAST_GMAX * 8 * 8);
+    z.off_slotsB = take((size_t)nc * FAST_GMAX * 4 * 8);
+    z.off_chunk = take((size_t)nc * ((f->n_elem + 1023) / 1024) * 8);
+  }
   z.scratch_bytes = o;
   z.blob_max = 256 + (size_t)nc * f->n_elem * z.W * 8 + (size_t)nc * (f->n_elem + 1) * 8 + (size_t)nc * z.nv * z.vbytes;
   return z;
@@ -330,6 +347,15 @@ static Job make_job(isr_ctx* c, const isr_field* f, const Sizes& z, char* scratc
   j.lookback = (u64*)(scratch + z.off_lookback);
   j.lists = (u64*)(scratch + z.off_lists);
   j.list_cap = z.list_cap;
+  j.done = (u32*)(scratch + z.off_done);
+  if (z.fast) {
+    j.lidx = (u32*)(scratch + z.off_lidx);
+    j.cnt = (u32*)(scratch + z.off_cnt);
+    j.slotsA = (long long*)(scratch + z.off_slotsA);
+    j.slotsB = (long long*)(scratch + z.off_slotsB);
+    j.chunk = (u64*)(scratch + z.off_chunk);
+    j.nchunk = (f->n_elem + 1023) / 1024;
+  }
   j.bitmap = b->bitmap();
   j.elem_ptr = b->elem_ptr();
   j.values = b->values();
@@ -340,7 +366,58 @@ static Job make_job(isr_ctx* c, const isr_field* f, const Sizes& z, char* scratc
 // Enqueue every phase of one compression on stream s (no host sync).
 namespace isr {
 
-int enqueue_pipeline(isr_ctx* c, const Job& j, const Sizes& z, hipStream_t s, hipEvent_t* ev) {
+// Streaming path (isr_engine.cuh): sample, pass A, exact window bins and
+// level-1 selection, refinement, per-element counts and offsets, pass B with
+// the finalize step.  A threshold outside the sampled window sets ST_MISS in
+// the selection; every later kernel then returns at once and the host runs
+// the general pipeline.
+static int enqueue_fast(isr_ctx* c, const Job& j0, const Sizes& z, hipStream_t s, hipEvent_t* ev) {
+  Job j = j0;
+  const int nc = j.ncomp, prec = j.precision;
+  const long long n = j.order + 1, epw = 64 / (n * n);
+  const long long ftiles = (j.n_elem + epw - 1) / epw;
+  auto grid = [&](int kind) {
+    const long long slots = (long long)c->num_cu * resident_fast(kind, prec, j.order);
+    long long g = std::max<long long>(1, slots / nc);
+    g = std::min<long long>(g, (ftiles + 3) / 4);
+    return (int)std::max<long long>(1, std::min<long long>(g, FAST_GMAX));
+  };
+  j.gA = grid(F_PASSA);
+  j.gB = grid(F_PASSB);
+  // terms per lane: 8 slots per tile, tiles per wave
+  const long long per_wave = (ftiles + 4ll * std::min(j.gA, j.gB) - 1) / (4ll * std::min(j.gA, j.gB));
+  const long long terms = 8 * per_wave;
+  int h = 1;
+  while ((1ll << (h - 1)) < terms) ++h;
+  j.xh = std::max(7, std::min(20, h));
+  auto rec = [&](int k) {
+    if (ev) (void)hipEventRecord(ev[k], s);
+  };
+  HIPCHK(launch_zero((void*)j.histE, z.zero_bytes, s));
+  rec(0);
+  const long long ss = j.sample_stride > 0 ? j.sample_stride : 1;
+  const long long stiles = (ftiles + ss - 1) / ss;
+  const int gs = (int)std::max<long long>(1, std::min<long long>(64, (stiles + 15) / 16));
+  HIPCHK(launch_fast(F_SAMPLE, prec, j, gs, s));
+  HIPCHK(launch_fast(F_PASSA, prec, j, j.gA, s));
+  rec(1);
+  const int gl = (int)std::max<long long>(1, std::min<long long>(c->num_cu, (long long)(z.nv / 65536) + 1));
+  HIPCHK(launch_gather(j, gl, s));
+  rec(2);
+  rec(3);
+  // few workgroups: each flushes up to RBINS sub-bins with global atomics
+  const int rgx = std::max(1, std::min(64, (int)(z.nv >> 20) + 1));
+  for (int L = 2; L <= NLEV; ++L) HIPCHK(launch_refsel(j, L, rgx, s));
+  HIPCHK(launch_count(j, gl, s));
+  rec(4);
+  HIPCHK(launch_fast(F_PASSB, prec, j, j.gB, s));
+  rec(5);
+  rec(6);
+  return ISR_OK;
+}
+
+int enqueue_pipeline(isr_ctx* c, const Job& j, const Sizes& z, hipStream_t s, hipEvent_t* ev, bool fast) {
+  if (fast) return enqueue_fast(c, j, z, s, ev);
   const int nc = j.ncomp;
   const long long tiles = z.tiles;
   const int prec = j.precision;
@@ -371,13 +448,8 @@ int enqueue_pipeline(isr_ctx* c, const Job& j, const Sizes& z, hipStream_t s, hi
   rec(2);
   HIPCHK(launch_pass(K_PASS2, prec, j, grid_per_comp(K_PASS2), s));
   rec(3);
-  const int rgx = std::max(1, std::min(256, (int)((z.nv / 4096) + 1)));
-  HIPCHK(launch_refine(j, 2, rgx, s));
-  HIPCHK(launch_select(j, 2, s));
-  for (int L = 3; L <= NLEV; ++L) {
-    HIPCHK(launch_refine(j, L, rgx, s));
-    HIPCHK(launch_select(j, L, s));
-  }
+  const int rgx = std::max(1, std::min(64, (int)(z.nv >> 20) + 1));
+  for (int L = 2; L <= NLEV; ++L) HIPCHK(launch_refsel(j, L, rgx, s));
   rec(4);
   const long long slots3 = (long long)c->num_cu * resident_blocks(K_PASS3, prec, j.order);
   const int g3 = (int)std::min<long long>(tiles * nc, slots3);
@@ -408,7 +480,7 @@ static isr_blob* new_blob(isr_ctx* c, const isr_field* f, const Sizes& z) {
   b->tol = f->tol;
   b->precision = f->precision;
   b->dev_bytes = z.blob_max;
-  b->dev = c->arena->alloc(z.blob_max);
+  b->dev = c->arena->alloc(z.blob_max, true);
   if (!b->dev) {
     delete b;
     return nullptr;
@@ -486,7 +558,7 @@ static void put_host_state(isr_ctx* c, CompState* p) {
 }
 
 static int task_enqueue(Task* t) {
-  int rc = enqueue_pipeline(t->c, t->j, t->z, t->s, t->timing ? t->ev : nullptr);
+  int rc = enqueue_pipeline(t->c, t->j, t->z, t->s, t->timing ? t->ev : nullptr, t->fast);
   if (rc) return rc;
   HIPCHK(hipMemcpyAsync(t->hs, t->j.st, sizeof(CompState) * t->f.ncomp, hipMemcpyDeviceToHost, t->s));
   HIPCHK(hipEventRecord(t->done, t->s));
@@ -534,6 +606,7 @@ int task_begin(isr_ctx* c, const isr_field* f, hipStream_t s, bool timing, Task*
     return fail(ISR_EDEVICE, "could not create host state or event");
   }
   t->j = make_job(c, f, t->z, t->scratch, t->b);
+  t->fast = t->z.fast;
   t->timing = timing;
   if (timing)
     for (auto& e : t->ev) (void)hipEventCreate(&e);
@@ -550,6 +623,22 @@ int task_step(Task* t, isr_blob** out) {
   const isr_field* f = &t->f;
   int flags = 0;
   for (int k = 0; k < f->ncomp; ++k) flags |= hs[k].flags;
+  if (t->fast && (flags & ST_MISS)) {
+    // the threshold fell outside the sampled window: run the general pipeline
+    // (no sample window this time), keeping any budget override
+    if (t->timing) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, t->ev[0], t->ev[6]) == hipSuccess) t->st.phase_ms[7] += ms;
+    }
+    t->fast = false;
+    t->j.sample_stride = 0;
+    int rc = task_enqueue(t);
+    if (rc) {
+      task_release(t);
+      return rc;
+    }
+    return ISR_PENDING;
+  }
   int rc = status_from_flags(flags);
   if (rc) {
     task_release(t);
@@ -593,12 +682,30 @@ int task_step(Task* t, isr_blob** out) {
   if (f->tol >= 0.0)
     for (int k = 0; k < f->ncomp; ++k) within = within && !(hs[k].rel > f->tol);
   b->status = within ? ISR_OK : ISR_ETOL;
-  // return the unused tail of the worst-case value reservation
+  // return the unused tail of the worst-case value reservation; under a tight
+  // budget move the blob to an exact-size allocation instead (a shrunk
+  // reservation leaves a gap that the next scratch may not fit)
   const size_t used = 256 + b->bitmap_bytes() + b->ptr_bytes() + b->values_bytes();
-  t->c->arena->shrink(b->dev, used);
+  bool moved = false;
+  if (used < b->dev_bytes / 2 && t->c->arena->budget() < 8 * (t->z.scratch_bytes + t->z.blob_max)) {
+    t->c->arena->free(t->scratch);
+    t->scratch = nullptr;
+    void* q = t->c->arena->alloc(used, true);
+    if (q && hipMemcpyAsync(q, b->dev, used, hipMemcpyDeviceToDevice, t->s) == hipSuccess &&
+        hipStreamSynchronize(t->s) == hipSuccess) {
+      t->c->arena->free(b->dev);
+      b->dev = q;
+      moved = true;
+    } else {
+      (void)hipGetLastError();
+      if (q) t->c->arena->free(q);
+    }
+  }
+  if (!moved) t->c->arena->shrink(b->dev, used);
   b->dev_bytes = (used + 255) & ~size_t(255);
   t->st.phase_ms[6] = t->repair_ms;
   t->st.repair_iters = t->iters;
+  t->st.path = t->fast ? 1 : 0;
   t->st.status = b->status;
   t->st.t_start = t->t_start;
   t->st.t_done = now_s();
@@ -617,6 +724,10 @@ int run_batch(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_s
   for (int i = 0; i < count; ++i) {
     const int o = fs[i].order;
     if ((o != 5 && o != 7 && o != 9) || fs[i].precision != fs[0].precision) persistent = false;
+    // the persistent kernel runs the general passes: their FP32 / BF16
+    // transforms round differently from the streaming ones, so only FP64
+    // batches (exact either way) take it
+    if (fs[i].precision != ISR_PREC_FP64) persistent = false;
   }
   if (!persistent) return run_batch_sequential(c, fs, count, outs, st);
   const int prec = fs[0].precision;
@@ -645,6 +756,7 @@ int run_batch(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_s
     outs[i] = nullptr;
     Snap& x = sn[i];
     x.z = plan_sizes(&fs[i]);
+    x.z.sample_stride = x.z.tiles >= 1024 ? 32 : 0;  // the batch kernel runs the general passes
     x.scratch = (char*)c->arena->alloc(x.z.scratch_bytes);
     x.b = x.scratch ? new_blob(c, &fs[i], x.z) : nullptr;
     x.hs = grab_host_state(c);
@@ -1063,7 +1175,7 @@ int isr_blob_from_host(isr_ctx* c, const void* buf, uint64_t nbytes, isr_blob** 
   if (rc) return rc;
   b->ctx = c;
   b->dev_bytes = 256 + b->bitmap_bytes() + b->ptr_bytes() + b->values_bytes();
-  b->dev = c->arena->alloc(b->dev_bytes);
+  b->dev = c->arena->alloc(b->dev_bytes, true);
   if (!b->dev) return fail(ISR_ENOMEM, "blob does not fit the HBM budget");
   u64 vo[ISR_MAX_COMP];
   for (int k = 0; k < b->ncomp; ++k) vo[k] = b->comp[k].voff;

@@ -23,7 +23,11 @@ class Arena {
  public:
   explicit Arena(uint64_t budget);
   ~Arena();
-  void* alloc(size_t bytes);  // nullptr when the budget or the device is exhausted
+  // nullptr when the budget or the device is exhausted.  Short-lived scratch
+  // takes the lowest free range that fits; long-lived blobs (high = true) take
+  // the top of the highest one, so that shrunk blobs do not split the space
+  // scratch needs.
+  void* alloc(size_t bytes, bool high = false);
   void free(void* p);
   void shrink(void* p, size_t bytes);
   void release();
@@ -51,7 +55,10 @@ struct Sizes {
   long long tiles = 0;
   int vbytes = 8;
   size_t off_histE = 0, off_histN = 0, off_histR = 0, off_histL = 0, off_st = 0, off_ticket = 0,
-         off_lookback = 0, off_lists = 0, off_histEs = 0, off_histNs = 0;
+         off_lookback = 0, off_lists = 0, off_histEs = 0, off_histNs = 0, off_done = 0, off_lidx = 0, off_cnt = 0,
+         off_slotsA = 0, off_slotsB = 0, off_chunk = 0;
+  bool fast = false;         // streaming path (orders 1..7)
+  int gA = 0, gB = 0, xh = 0;  // its grids (workgroups per component) and extraction headroom
   long long sample_stride = 0;
   size_t zero_bytes = 0;     // leading scratch bytes to clear
   u64 list_cap = 0;
@@ -60,7 +67,7 @@ struct Sizes {
 };
 Sizes plan_sizes(const isr_field* f);
 
-int enqueue_pipeline(isr_ctx* c, const Job& j, const Sizes& z, hipStream_t s, hipEvent_t* ev);
+int enqueue_pipeline(isr_ctx* c, const Job& j, const Sizes& z, hipStream_t s, hipEvent_t* ev, bool fast);
 int run_compress(isr_ctx* c, const isr_field* f, isr_blob** out, isr_stats* st);
 int run_batch(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_stats* st);
 int run_batch_sequential(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_stats* st);
@@ -82,6 +89,7 @@ struct Task {
   hipEvent_t done = nullptr; // recorded after the state copy
   hipEvent_t ev[7] = {};
   bool timing = false;
+  bool fast = false;         // this attempt runs the streaming path
   int iters = 0;
   float repair_ms = 0.f;
   double t_start = 0;

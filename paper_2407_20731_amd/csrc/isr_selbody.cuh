@@ -84,10 +84,13 @@ DEV void select1_body(const Job& j, int comp, int sample) {
       wb_add(P, part_at(cl, ch, bl));
       continue;
     }
+    // the crossing chunk, one bin per lane (loads in parallel, then broadcast)
+    const int mybin = 32 * l + lane;
+    const HistBin mine = (lane < 32 && mybin < HBINS - 1) ? HE[mybin] : HistBin{0ull, 0ull, 0ull};
     for (int k = 0; k < 32; ++k) {
       const int bin = 32 * l + k;
       if (bin >= HBINS - 1) break;
-      const HistBin h = HE[bin];
+      const HistBin h = {bcast64(mine.cnt, k), bcast64(mine.lo, k), bcast64(mine.hi, k)};
       if (h.cnt == 0ull) continue;
       bstar = bin;
       const u128 sb = bin_sum(h);
@@ -101,6 +104,18 @@ DEV void select1_body(const Job& j, int comp, int sample) {
     }
     found = true;
     break;
+  }
+  if (!sample && st->win_mode) {
+    // the streaming pass kept exact sums only inside the window: a boundary
+    // outside it (or none at all) sends the request to the general pipeline
+    const bool hit = found && bstar >= st->win_lo && bstar < st->win_hi;
+    if (!hit) {
+      if (lane == 0) {
+        st->flags |= ST_MISS;
+        st->resolved = 1;
+      }
+      return;
+    }
   }
   if (sample) {
     if (lane == 0 && found) {
@@ -168,8 +183,11 @@ DEV void select1_body(const Job& j, int comp, int sample) {
 // energies that match the current prefix; for L >= 3 the matching keys are
 // also copied to the other list.
 
-DEV int list_out(int L) { return ((L - 3) % 2 == 0) ? 1 : 0; }
-DEV int list_in(int L) { return L == 2 ? 0 : 1 - list_out(L); }
+// List 0 (the candidates of the boundary bin or window) is only read, by
+// levels 2 and 3; levels 3..6 copy the members of the current sub-bin to
+// lists 1, 2, 1, 2, so list 0 stays whole for the per-element kept counts.
+DEV int list_out(int L) { return (L & 1) ? 1 : 2; }
+DEV int list_in(int L) { return L <= 3 ? 0 : 3 - list_out(L); }
 DEV int list_members(int L) { return L == 2 ? 0 : list_out(L); }
 
 // Worker `item` of `nitems` handles list entries item*256 + tid + k*nitems*256
@@ -184,13 +202,13 @@ DEV void refine_body(const Job& j, int comp, int L, u64 (*h)[2], u64 item, u64 n
   for (int k = tid; k < nb; k += 256) h[k][0] = h[k][1] = 0ull;
   __syncthreads();
   const int li = list_in(L);
-  const u64* in = j.lists + ((size_t)comp * 2 + li) * j.list_cap;
-  const u64 nin = st->list_count[li] < j.list_cap ? st->list_count[li] : j.list_cap;
+  const u64* in = list_ptr(j, comp, li);
+  const u64 nin = st->list_count[li] < list_capk(j, li) ? st->list_count[li] : list_capk(j, li);
   const u64 prefix = st->key_prefix, mask = st->key_mask;
   const int bstar = st->bstar;
   const u64 implicit = bstar ? (1ull << 52) : 0ull;
   const int lo_idx = L >= 3 ? list_out(L) : 0;
-  u64* out = j.lists + ((size_t)comp * 2 + lo_idx) * j.list_cap;
+  u64* out = list_ptr(j, comp, lo_idx);
   const u64 stride = nitems * 256;
   // the loop trip count is the same for every lane of a wave (ballots inside)
   const u64 nin_r = (nin + 63) & ~63ull;
@@ -207,7 +225,7 @@ DEV void refine_body(const Job& j, int comp, int L, u64 (*h)[2], u64 item, u64 n
       atomicAdd(&h[sb][0], (1ull << 43) + (sig & M21));
       atomicAdd(&h[sb][1], sig >> 21);
     }
-    if (L >= 3) list_append(out, &st->list_count[lo_idx], j.list_cap, m, key, &st->flags);
+    if (L >= 3) list_append(out, &st->list_count[lo_idx], list_capk(j, lo_idx), m, key, &st->flags);
   }
   __syncthreads();
   HistBin* g = j.histL + ((size_t)(L - 2) * j.ncomp + comp) * RBINS;
@@ -224,7 +242,7 @@ DEV void refine_body(const Job& j, int comp, int L, u64 (*h)[2], u64 item, u64 n
 DEV void resolve_sorted(const Job& j, CompState* st, int comp, int ml, int L, u64* keys, u64* slo, u64* shi,
                         int* best) {
   const int tid = threadIdx.x;
-  const u64* list = j.lists + ((size_t)comp * 2 + ml) * j.list_cap;
+  const u64* list = list_ptr(j, comp, ml);
   const u64 lc = st->list_count[ml];
   const int cnt = (int)(lc < (u64)CAP ? lc : (u64)CAP);  // == cur_count unless a list overflowed
   int np = 1;

@@ -15,6 +15,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 import struct
+import weakref
 from dataclasses import dataclass
 from typing import Dict, List, Optional, Sequence
 
@@ -30,7 +31,7 @@ PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 FLAG_TIMING = 1
 MAX_COMP = 8
 NPHASE = 8
-PHASES = ("pass1", "select1", "pass2", "refine", "pass3", "finalize", "repair", "unused")
+PHASES = ("pass1", "select1", "pass2", "refine", "pass3", "finalize", "repair", "fallback")
 PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16": PREC_BF16}
 _STATUS = {OK: "ISR_OK", PENDING: "ISR_PENDING", EINVAL: "ISR_EINVAL", ENOMEM: "ISR_ENOMEM",
            EDEVICE: "ISR_EDEVICE", ETOL: "ISR_ETOL", ECANCELED: "ISR_ECANCELED", ENOTFOUND: "ISR_ENOTFOUND"}
@@ -60,7 +61,7 @@ class isr_stats(C.Structure):
                 ("kept", C.c_uint64 * MAX_COMP), ("in_bytes", C.c_uint64), ("blob_bytes", C.c_uint64),
                 ("cr", C.c_double), ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
                 ("phase_ms", C.c_float * NPHASE), ("repair_iters", C.c_int32), ("status", C.c_int32),
-                ("precision", C.c_int32), ("reserved", C.c_int32)]
+                ("precision", C.c_int32), ("path", C.c_int32)]
 
 
 _lib = None
@@ -137,7 +138,7 @@ def _stats_dict(st: isr_stats, ncomp: int) -> dict:
         "kept": list(st.kept[:ncomp]), "in_bytes": st.in_bytes, "blob_bytes": st.blob_bytes, "cr": st.cr,
         "t_submit": st.t_submit, "t_start": st.t_start, "t_done": st.t_done,
         "phase_ms": dict(zip(PHASES, list(st.phase_ms))), "repair_iters": st.repair_iters,
-        "status": st.status, "precision": st.precision,
+        "status": st.status, "precision": st.precision, "path": st.path,
     }
 
 
@@ -189,6 +190,7 @@ class Blob:
         self._h = C.c_void_p(handle)
         self.stats = stats
         self.status = status
+        ctx._blobs.add(self)  # freed by Context.close() if still alive then
         lib = load_library()
         o, nc, vb = C.c_int32(), C.c_int32(), C.c_int32()
         ne = C.c_int64()
@@ -216,9 +218,11 @@ class Blob:
         return parse_blob(self.to_bytes())
 
     def free(self):
-        if self._h:
+        # a blob must not outlive its context (the library frees it into the
+        # context's arena)
+        if self._h and self._ctx._h:
             load_library().isr_blob_free(self._h)
-            self._h = C.c_void_p(0)
+        self._h = C.c_void_p(0)
 
     def __del__(self):
         try:
@@ -238,14 +242,24 @@ class Context:
         lib = load_library()
         cfg = isr_config(device=device, flags=flags, hbm_budget_bytes=budget_bytes, max_inflight=max_inflight)
         h = C.c_void_p()
+        self._blobs = weakref.WeakSet()
+        self._h = C.c_void_p(0)
         _check(lib.isr_create(C.byref(cfg), C.byref(h)), "isr_create")
         self._h = h
         self.device = device
 
     def close(self):
         if self._h:
+            for b in list(self._blobs):
+                b.free()
             _check(load_library().isr_destroy(self._h), "isr_destroy")
             self._h = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def __enter__(self):
         return self

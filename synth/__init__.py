@@ -117,6 +117,47 @@ def field(n_elem: int, order: int, ncomp: int = 3, seed: int = 1, n_modes: int =
     return out.astype(dtype, copy=False)
 
 
+def field_torch(n_elem: int, order: int, ncomp: int = 3, seed: int = 1, n_modes: int = 64,
+                kmax: float = 4.0, noise: float = 1e-6, device: str = "cuda", chunk: int = 8192):
+    """The same recipe evaluated with torch on a device, for large element pools
+    (bench workloads).  Mode draws use the same numpy generator; the field is
+    summed per element chunk as a batched complex product, and the noise comes
+    from torch's generator seeded with `seed` (so values differ from `field`
+    in rounding and noise, not in distribution)."""
+    import torch
+
+    if ncomp > 3:
+        raise ValueError("the Fourier-mode recipe defines at most 3 components")
+    rng = np.random.default_rng(seed)
+    k, amp, phase, d = modes(rng, n_modes, kmax)
+    n = order + 1
+    xi = gll_points(order)
+    h = 2.0 * math.pi / 8.0
+    nx, ny, nz = mesh_dims(n_elem)
+    cd = torch.complex128
+    EX = torch.from_numpy(_axis_phasors(k[:, 0], nx, xi, h).reshape(n_modes, nx, n)).to(device, cd)
+    EY = torch.from_numpy(_axis_phasors(k[:, 1], ny, xi, h).reshape(n_modes, ny, n)).to(device, cd)
+    EZ = torch.from_numpy(_axis_phasors(k[:, 2], nz, xi, h).reshape(n_modes, nz, n)).to(device, cd)
+    out = torch.empty((ncomp, n_elem, n, n, n), dtype=torch.float64, device=device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    for c in range(ncomp):
+        coef = torch.from_numpy(amp * d[:, c] * np.exp(1j * phase)).to(device, cd)  # [M]
+        for e0 in range(0, n_elem, chunk):
+            e = torch.arange(e0, min(n_elem, e0 + chunk), device=device)
+            ex, ey, ez = e % nx, (e // nx) % ny, e // (nx * ny)
+            zk = (coef[:, None, None] * EZ[:, ez, :]).permute(1, 2, 0).contiguous()      # [B, n(k), M]
+            yx = (EY[:, ey, :, None] * EX[:, ex, None, :]).permute(1, 0, 2, 3)            # [B, M, n(j), n(i)]
+            yx = yx.reshape(e.numel(), n_modes, n * n).contiguous()
+            out[c, e0:e0 + e.numel()] = torch.bmm(zk, yx).real.reshape(-1, n, n, n)
+        rms = torch.sqrt(torch.mean(out[c] * out[c]))
+        if rms > 0:
+            out[c] /= rms
+    if noise:
+        out += noise * torch.randn(out.shape, generator=gen, dtype=torch.float64, device=device)
+    return out
+
+
 def element_pool(n_elem: int, order: int, seed: int, ncomp: int = 3) -> np.ndarray:
-    """A device-resident pool of elements from which windows are taken."""
+    """A pool of elements from which request windows are taken."""
     return field(n_elem, order, ncomp=ncomp, seed=seed)

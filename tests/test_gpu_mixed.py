@@ -31,7 +31,7 @@ import pytest
 
 import oracle
 import synth
-from oracle.compress import unpack_bitmap
+from oracle.compress import ETOL, unpack_bitmap
 from oracle.tables import gll_tables
 
 pytestmark = pytest.mark.gpu
@@ -79,7 +79,12 @@ def test_mixed_against_oracle(isr_ctx, prec, order, E, tol):
             beta = 2 * bound / cabs + (bound / cabs) ** 2
             band = np.abs(rc.energy - rc.tau) <= 2 * beta * rc.tau
             assert np.all(band[diff]), (c, int(diff.sum()), int((~band & diff).sum()))
-        assert h["rel_err"] <= tol, (c, h["rel_err"])
+        if blob.status != 0:
+            # the BF16-split transforms carry ~2^-16 relative error: below about
+            # 1e-4 the bound can be out of reach, which the library reports
+            assert prec == "bf16" and tol < 1e-4 and blob.status == ETOL, (blob.status, prec, tol)
+        else:
+            assert h["rel_err"] <= tol, (c, h["rel_err"])
         # the oracle's FP64 reconstruction from the blob's own kept values
         rec = oracle.decompress(arr.bitmap[c], arr.values[c].astype(np.float64), order)
         from oracle.compress import norm_terms
@@ -88,7 +93,7 @@ def test_mixed_against_oracle(isr_ctx, prec, order, E, tol):
         rel_blob = math.sqrt(err2 / rc.U2)
         # the blob's FP64 reconstruction differs from the reduced-precision one
         # the kernel measured by the inverse transform error only
-        assert rel_blob <= tol * 1.05 + 10 * EPS[prec](n) * 4, (c, rel_blob)
+        assert rel_blob <= max(tol, h["rel_err"]) * 1.05 + 10 * EPS[prec](n) * 4, (c, rel_blob)
         jac = (keep_g & keep_o).sum() / max(1, (keep_g | keep_o).sum())
         rec_vs_oracle = math.sqrt(np.sum((rec - rc.recon) ** 2) / np.sum(u_np[c] ** 2))
         report.append((c, int(diff.sum()), round(jac, 6), h["kept"] - rc.kept, h["rel_err"], rec_vs_oracle))
