@@ -69,6 +69,7 @@ struct Eng {
   static constexpr int NB = MF ? 2 : 1;    // pencil blocks (32 pencils each on MFMA)
   static constexpr int SPB = MF ? 4 : n;   // registers per block
   static constexpr int NS = NB * SPB;      // slots per lane
+  static_assert(NS <= 8, "slot tables hold 8 slots");
   static constexpr int P0 = n + 1;         // LDS row pitch
   static constexpr int LDSW = EPW * n * n * P0;
   static constexpr int W = (n3 + 63) / 64;  // bitmap words per element
@@ -312,14 +313,18 @@ struct Eng {
   }
 };
 
-// w3 and g3 of one order in LDS (read per slot; registers would cost 4 NS).
+// w3 and g3 of every (slot, lane) in LDS, slot-major so that the 64 lanes of
+// a read hit 64 consecutive doubles (registers would cost 4 NS VGPRs).
 struct TabLds {
-  double w3[512], g3[512];
+  double w3[8][64], g3[8][64];
 };
-DEV void tab_load(TabLds& T, const DevTables& t, int n3, int tid) {
-  for (int k = tid; k < n3; k += 256) {
-    T.w3[k] = t.w3[k];
-    T.g3[k] = t.g3[k];
+template <class G>
+DEV void tab_load(TabLds& T, const DevTables& t, int tid) {
+  for (int k = tid; k < G::NS * 64; k += 256) {
+    const int s = k >> 6, l = k & 63;
+    const bool v = G::pvalid(s, l);
+    T.w3[s][l] = v ? t.w3[G::w3i(s, l)] : 0.0;
+    T.g3[s][l] = v ? t.g3[G::g3i(s, l)] : 0.0;
   }
 }
 
@@ -426,7 +431,7 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_sample(Job j) {
   if (tid == 0) L.maxe = 0;
   typename G::Mats mt;
   G::init(mt, j.tab, lane);
-  tab_load(L.tab, j.tab, n3, tid);
+  tab_load<G>(L.tab, j.tab, tid);
   __syncthreads();
   __syncthreads();
   const long long E = j.n_elem, tiles = (E + EPW - 1) / EPW;
@@ -446,7 +451,7 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_sample(Job j) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       if (!G::valid(s, lane, ne)) continue;
-      const double x = jw(j.jac, e0 + G::elem(s, lane), L.tab.w3[G::w3i(s, lane)]) * (u[s] * u[s]);
+      const double x = jw(j.jac, e0 + G::elem(s, lane), L.tab.w3[s][lane]) * (u[s] * u[s]);
       u2 += x;
       const int ex = bits_exp(dbits(x));
       maxe = ex > maxe ? ex : maxe;
@@ -455,7 +460,7 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_sample(Job j) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const bool v = G::valid(s, lane, ne);
-      const double en = v ? jw(j.jac, e0 + G::elem(s, lane), L.tab.g3[G::g3i(s, lane)]) * (c[s] * c[s]) : 0.0;
+      const double en = v ? jw(j.jac, e0 + G::elem(s, lane), L.tab.g3[s][lane]) * (c[s] * c[s]) : 0.0;
       const int b = bits_exp(dbits(en));
       if (v && b < HBINS - 1) {  // rounded sums only place the window
         atomicAdd(&L.hc[b], 1u);
@@ -539,7 +544,7 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passA(Job j) {
   u32* cnt = j.cnt + (size_t)comp * E;
   typename G::Mats mt;
   G::init(mt, j.tab, lane);
-  tab_load(L.tab, j.tab, n3, tid);
+  tab_load<G>(L.tab, j.tab, tid);
   __syncthreads();
   XAcc an = {0.0, 0.0, 0.0}, ae = {0.0, 0.0, 0.0};
   u64 hi_tot = 0ull;
@@ -547,14 +552,25 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passA(Job j) {
   const double* ub = j.u + (size_t)comp * j.comp_stride;
   const bool vec = ((((uintptr_t)ub) & 15) == 0);
   const long long nw = (long long)gridDim.x * 4;
+  // the next tile's field values are loaded while this one is processed
+  double un[NS];
+  {
+    const long long t0 = (long long)blockIdx.x * 4 + wv;
+    if (t0 < tiles) G::load(ub + t0 * EPW * n3, (int)((E - t0 * EPW) < EPW ? (E - t0 * EPW) : EPW), vec, un, lane);
+  }
   for (long long t = (long long)blockIdx.x * 4 + wv; t < tiles; t += nw) {
     const long long e0 = t * EPW;
     const int ne = (int)((E - e0) < EPW ? (E - e0) : EPW);
     double u[NS], c[NS];
-    G::load(ub + e0 * n3, ne, vec, u, lane);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) u[s] = un[s];
+    if (t + nw < tiles) {
+      const long long e1 = (t + nw) * EPW;
+      G::load(ub + e1 * n3, (int)((E - e1) < EPW ? (E - e1) : EPW), vec, un, lane);
+    }
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      const double x = G::valid(s, lane, ne) ? jw(j.jac, e0 + G::elem(s, lane), L.tab.w3[G::w3i(s, lane)]) * (u[s] * u[s]) : 0.0;
+      const double x = G::valid(s, lane, ne) ? jw(j.jac, e0 + G::elem(s, lane), L.tab.w3[s][lane]) * (u[s] * u[s]) : 0.0;
       const double r = xadd_r(an, PN, x);
       if (r != 0.0) slow_bin(gN, r);
       // one slot at a time: interleaving them would hold every slot's
@@ -570,7 +586,7 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passA(Job j) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const bool v = G::valid(s, lane, ne);
-      const double en = v ? jw(j.jac, e0 + G::elem(s, lane), L.tab.g3[G::g3i(s, lane)]) * (c[s] * c[s]) : 0.0;
+      const double en = v ? jw(j.jac, e0 + G::elem(s, lane), L.tab.g3[s][lane]) * (c[s] * c[s]) : 0.0;
       const u64 key = dbits(en);
       const int ex = bits_exp(key);
       const bool hi = v && ex >= whi;
@@ -629,6 +645,7 @@ struct PassBLds {
   u64 bm[4][16];
   u32 wp[4][16];
   long long red[4][8];
+  __int128 part[256];
   int last;
 };
 
@@ -653,7 +670,7 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passB(Job j) {
   u64* gbm = j.bitmap + (size_t)comp * E * W;
   typename G::Mats mt;
   G::init(mt, j.tab, lane);
-  tab_load(L.tab, j.tab, n3, tid);
+  tab_load<G>(L.tab, j.tab, tid);
   __syncthreads();
   XAcc ar = {0.0, 0.0, 0.0};
   bool bad = false;
@@ -662,17 +679,28 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passB(Job j) {
   const long long nw = (long long)gridDim.x * 4;
   u64* bm = L.bm[wv];
   u32* wp = L.wp[wv];
+  // the next tile's field values are loaded while this one is processed
+  double un[NS];
+  {
+    const long long t0 = (long long)blockIdx.x * 4 + wv;
+    if (t0 < tiles) G::load(ub + t0 * EPW * n3, (int)((E - t0 * EPW) < EPW ? (E - t0 * EPW) : EPW), vec, un, lane);
+  }
   for (long long t = (long long)blockIdx.x * 4 + wv; t < tiles; t += nw) {
     const long long e0 = t * EPW;
     const int ne = (int)((E - e0) < EPW ? (E - e0) : EPW);
     double u[NS], c[NS];
-    G::load(ub + e0 * n3, ne, vec, u, lane);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) u[s] = un[s];
+    if (t + nw < tiles) {
+      const long long e1 = (t + nw) * EPW;
+      G::load(ub + e1 * n3, (int)((E - e1) < EPW ? (E - e1) : EPW), vec, un, lane);
+    }
     G::forward(u, c, L.buf[wv], mt, j.tab, lane);
     bool keep[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const bool v = G::valid(s, lane, ne);
-      const double en = v ? jw(j.jac, e0 + G::elem(s, lane), L.tab.g3[G::g3i(s, lane)]) * (c[s] * c[s]) : 0.0;
+      const double en = v ? jw(j.jac, e0 + G::elem(s, lane), L.tab.g3[s][lane]) * (c[s] * c[s]) : 0.0;
       keep[s] = v && dbits(en) >= tk;
     }
     if constexpr (G::n == 8) {
@@ -709,21 +737,27 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passB(Job j) {
       u64 mine = 0ull;
 #pragma unroll
       for (int r = 0; r < 8; ++r) mine = lane == r ? word[r] : mine;
+      // bits below this lane's pencil in its words (one mask per pencil block)
+      u64 below[G::NB];
+#pragma unroll
+      for (int blk = 0; blk < G::NB; ++blk) below[blk] = (1ull << G::pencil(blk * G::SPB, lane)) - 1ull;
       if (lane < 8) gbm[e0 * 8 + lane] = mine;
       const u64 ebase = eptr[e0];
       if ((u64)tot != eptr[e0 + 1] - ebase) bad = true;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         if (!keep[s]) continue;
-        const int PI = G::pencil(s, lane), ax = G::axis(s, lane);
-        u64 wd = 0ull;
-        u32 pr = 0u;
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          wd = ax == r ? word[r] : wd;
-          pr = ax == r ? pre[r] : pr;
+        u64 wd;
+        u32 pr;
+        if constexpr (G::MF) {  // index r = 4 (g & 1) + (s & 3): one of two words
+          const bool up = (lane >> 4) & 1;
+          wd = up ? word[4 + (s & 3)] : word[s & 3];
+          pr = up ? pre[4 + (s & 3)] : pre[s & 3];
+        } else {
+          wd = word[s];
+          pr = pre[s];
         }
-        const u64 pos = voff + ebase + pr + (u64)__popcll(wd & ((1ull << PI) - 1ull));
+        const u64 pos = voff + ebase + pr + (u64)__popcll(wd & below[s / G::SPB]);
         if (pos >= vcap) {  // offsets disagree with the bitmap: never write past the values
           bad = true;
           continue;
@@ -779,7 +813,7 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passB(Job j) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const double d = u[s] - ut[s];
-      const double x = G::valid(s, lane, ne) ? jw(j.jac, e0 + G::elem(s, lane), L.tab.w3[G::w3i(s, lane)]) * (d * d) : 0.0;
+      const double x = G::valid(s, lane, ne) ? jw(j.jac, e0 + G::elem(s, lane), L.tab.w3[s][lane]) * (d * d) : 0.0;
       const double r = xadd_r(ar, PR, x);
       if (r != 0.0) slow_bin(gR, r);
       __builtin_amdgcn_sched_barrier(0);
@@ -794,12 +828,9 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passB(Job j) {
   if (tid < 3) j.slotsB[((size_t)comp * j.gB + blockIdx.x) * 4 + tid] = L.red[0][tid];
   if (!last_block(j.done + D_PASSB * 8 + comp, &L.last, gridDim.x)) return;
   // the component's error total, then its final statistics
-  if (tid == 0) {
-    __int128 K[3] = {0, 0, 0};
-    for (int b = 0; b < j.gB; ++b)
-      for (int k = 0; k < 3; ++k) K[k] += (__int128)j.slotsB[((size_t)comp * j.gB + b) * 4 + k];
-    emit_total(gR, K, PR.m, PR.h, -1);
-  }
+  __int128 K[3];
+  for (int k = 0; k < 3; ++k) K[k] = block_total_rows(j.slotsB + (size_t)comp * j.gB * 4, j.gB, 4, k, L.part, tid);
+  if (tid == 0) emit_total(gR, K, PR.m, PR.h, -1);
   __threadfence();
   __syncthreads();
   if (tid < 64) finalize_body(j, comp);

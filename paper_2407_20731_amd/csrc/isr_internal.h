@@ -120,6 +120,7 @@ struct Job {
   long long* slotsB;   // [ncomp][gB][4]
   u32* done;           // [16][8] finished-workgroup counters
   u64* chunk;          // [ncomp][nchunk] element-offset scan: chunk sums, then offsets
+  u64* gslot;          // [ncomp][GATHER_GMAX][16] per-workgroup window-bin partials
   long long nchunk;
   int gA, gB;          // workgroups per component of the two streaming passes
   int xh;              // extraction headroom (log2 of twice the terms per lane)
@@ -190,6 +191,7 @@ enum FastKind { F_SAMPLE = 0, F_PASSA = 1, F_PASSB = 2 };
 enum DoneSlot { D_SAMPLE = 0, D_GATHER = 1, D_COUNT = 2, D_PASSB = 3, D_REFSEL = 4 };  // D_REFSEL + level
 constexpr int FAST_MAX_ORDER = 7;
 constexpr int FAST_GMAX = 2048;  // workgroups per component of a streaming pass
+constexpr int GATHER_GMAX = 256;  // workgroups per component of the window-bin gather
 hipError_t launch_fast(int kind, int precision, const Job& j, int grid_x, hipStream_t s);
 int resident_fast(int kind, int precision, int order);
 hipError_t launch_fast_fp64(int kind, const Job& j, int grid_x, hipStream_t s);

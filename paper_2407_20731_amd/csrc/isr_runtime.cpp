@@ -312,6 +312,7 @@ Sizes plan_sizes(const isr_field* f) {
     z.off_slotsA = take((size_t)nc * FAST_GMAX * 8 * 8);
     z.off_slotsB = take((size_t)nc * FAST_GMAX * 4 * 8);
     z.off_chunk = take((size_t)nc * ((f->n_elem + 1023) / 1024) * 8);
+    z.off_gslot = take((size_t)nc * GATHER_GMAX * 16 * 8);
   }
   z.scratch_bytes = o;
   z.blob_max = 256 + (size_t)nc * f->n_elem * z.W * 8 + (size_t)nc * (f->n_elem + 1) * 8 + (size_t)nc * z.nv * z.vbytes;
@@ -354,6 +355,7 @@ static Job make_job(isr_ctx* c, const isr_field* f, const Sizes& z, char* scratc
     j.slotsA = (long long*)(scratch + z.off_slotsA);
     j.slotsB = (long long*)(scratch + z.off_slotsB);
     j.chunk = (u64*)(scratch + z.off_chunk);
+    j.gslot = (u64*)(scratch + z.off_gslot);
     j.nchunk = (f->n_elem + 1023) / 1024;
   }
   j.bitmap = b->bitmap();
@@ -401,7 +403,8 @@ static int enqueue_fast(isr_ctx* c, const Job& j0, const Sizes& z, hipStream_t s
   HIPCHK(launch_fast(F_SAMPLE, prec, j, gs, s));
   HIPCHK(launch_fast(F_PASSA, prec, j, j.gA, s));
   rec(1);
-  const int gl = (int)std::max<long long>(1, std::min<long long>(c->num_cu, (long long)(z.nv / 65536) + 1));
+  // list passes over ~2 % of the values
+  const int gl = (int)std::max<long long>(1, std::min<long long>(GATHER_GMAX, (long long)(z.nv >> 17) + 1));
   HIPCHK(launch_gather(j, gl, s));
   rec(2);
   rec(3);

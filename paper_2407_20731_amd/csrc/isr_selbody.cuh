@@ -212,20 +212,29 @@ DEV void refine_body(const Job& j, int comp, int L, u64 (*h)[2], u64 item, u64 n
   const u64 stride = nitems * 256;
   // the loop trip count is the same for every lane of a wave (ballots inside)
   const u64 nin_r = (nin + 63) & ~63ull;
-  for (u64 i = item * 256 + tid; i < nin_r; i += stride) {
-    u64 key = 0;
-    bool m = false;
-    if (i < nin) {
-      key = in[i];
-      m = (key & mask) == prefix;
+  // four entries per lane per step, loaded before any is used
+  constexpr int U = 4;
+  for (u64 i0 = item * 256 + tid; i0 < nin_r; i0 += U * stride) {
+    u64 keys[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const u64 i = i0 + u * stride;
+      keys[u] = i < nin ? in[i] : 0ull;
     }
-    if (m) {
-      const u64 sig = (key & M52) | implicit;
-      const int sb = (int)((key >> sh) & fmask);
-      atomicAdd(&h[sb][0], (1ull << 43) + (sig & M21));
-      atomicAdd(&h[sb][1], sig >> 21);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const u64 i = i0 + u * stride;
+      const u64 key = keys[u];
+      const bool m = i < nin && (key & mask) == prefix;
+      if (m) {
+        const u64 sig = (key & M52) | implicit;
+        const int sb = (int)((key >> sh) & fmask);
+        atomicAdd(&h[sb][0], (1ull << 43) + (sig & M21));
+        atomicAdd(&h[sb][1], sig >> 21);
+      }
+      // (i < nin_r is the same for every lane of a wave: ballots inside)
+      if (L >= 3 && i < nin_r) list_append(out, &st->list_count[lo_idx], list_capk(j, lo_idx), m, key, &st->flags);
     }
-    if (L >= 3) list_append(out, &st->list_count[lo_idx], list_capk(j, lo_idx), m, key, &st->flags);
   }
   __syncthreads();
   HistBin* g = j.histL + ((size_t)(L - 2) * j.ncomp + comp) * RBINS;

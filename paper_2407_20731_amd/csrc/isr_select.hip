@@ -90,27 +90,13 @@ __global__ __launch_bounds__(256) void k_gather(Job j) {
     if (lane == 0) red[wv][k] = w;
   }
   __syncthreads();
-  if (tid < 9) {
-    const u64 w = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-    const int b = wlo + tid / 3;
-    if (w && b < whi) {
-      if (tid % 3 == 0) atomicAdd(&gE[b].cnt, w);
-      if (tid % 3 == 1) atomicAdd(&gE[b].lo, w);
-      if (tid % 3 == 2) atomicAdd(&gE[b].hi, w);
-    }
-  }
+  // per-workgroup partials (no contended atomics); the last workgroup adds them
+  if (tid < 9) j.gslot[((size_t)comp * GATHER_GMAX + blockIdx.x) * 16 + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
   if (blockIdx.x == 0) {
     // totals of pass A's workgroup sums: fields 0..2 norm, 3..5 energy, 6 count
     for (int f = 0; f < 7; ++f) {
-      __int128 p = 0;
-      for (int b = tid; b < j.gA; b += 256) p += (__int128)j.slotsA[((size_t)comp * j.gA + b) * 8 + f];
-      part[tid] = p;
-      __syncthreads();
-      for (int d = 128; d > 0; d >>= 1) {
-        if (tid < d) part[tid] += part[tid + d];
-        __syncthreads();
-      }
-      if (tid == 0) red[0][f] = (u64)part[0], red[1][f] = (u64)((unsigned __int128)part[0] >> 64);
+      const __int128 t = block_total_rows(j.slotsA + (size_t)comp * j.gA * 8, j.gA, 8, f, part, tid);
+      if (tid == 0) red[0][f] = (u64)t, red[1][f] = (u64)((unsigned __int128)t >> 64);
       __syncthreads();
     }
     if (tid == 0) {
@@ -124,6 +110,18 @@ __global__ __launch_bounds__(256) void k_gather(Job j) {
     }
   }
   if (!last_block(j.done + D_GATHER * 8 + comp, &last, gridDim.x)) return;
+  for (int k = 0; k < 9; ++k) {
+    const u64 w = (u64)block_total_rows((const long long*)j.gslot + (size_t)comp * GATHER_GMAX * 16, gridDim.x, 16,
+                                        k, part, tid);
+    const int b = wlo + k / 3;
+    if (tid == 0 && w && b < whi) {
+      if (k % 3 == 0) atomicAdd(&gE[b].cnt, w);
+      if (k % 3 == 1) atomicAdd(&gE[b].lo, w);
+      if (k % 3 == 2) atomicAdd(&gE[b].hi, w);
+    }
+  }
+  __threadfence();
+  __syncthreads();
   if (tid < 64) select1_body(j, comp, 0);
   __syncthreads();
   if (tid == 0) {
@@ -250,12 +248,13 @@ hipError_t launch_refsel(const Job& j, int L, int gx, hipStream_t s) {
 }
 
 hipError_t launch_gather(const Job& j, int gx, hipStream_t s) {
+  if (gx > GATHER_GMAX) gx = GATHER_GMAX;
   hipLaunchKernelGGL(k_gather, dim3(gx, j.ncomp), dim3(256), 0, s, j);
   return hipGetLastError();
 }
 
 hipError_t launch_count(const Job& j, int gx, hipStream_t s) {
-  hipLaunchKernelGGL(k_count, dim3(gx, j.ncomp), dim3(256), 0, s, j);
+  hipLaunchKernelGGL(k_count, dim3(gx, j.ncomp), dim3(256), 0, s, j);  // independent atomics: many workgroups
   const long long nch = (j.n_elem + SCAN_CHUNK - 1) / SCAN_CHUNK;
   const int g = (int)(nch < 1024 ? nch : 1024);
   hipLaunchKernelGGL(k_scan1, dim3(g, j.ncomp), dim3(256), 0, s, j);

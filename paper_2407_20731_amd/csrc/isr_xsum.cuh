@@ -29,15 +29,19 @@ struct XParm {
   int m, h;
 };
 
+// 2^k for a normal exponent k, built from its bits (scalar instructions, so the
+// parameters stay in scalar registers)
+DEV double pow2(int k) { return __longlong_as_double((long long)(k + 1023) << 52); }
+
 DEV XParm xparm(int m, int h) {
   XParm P;
   P.m = m;
   P.h = h;
-  P.M = ldexp(1.0, m);
-  P.S1 = ldexp(1.0, m + h);
-  P.S2 = ldexp(1.0, m + 2 * h - 53);
-  P.S3 = ldexp(1.0, m + 3 * h - 106);
-  P.u3 = ldexp(1.0, m + 3 * h - 159);
+  P.M = pow2(m);
+  P.S1 = pow2(m + h);
+  P.S2 = pow2(m + 2 * h - 53);
+  P.S3 = pow2(m + 3 * h - 106);
+  P.u3 = pow2(m + 3 * h - 159);
   return P;
 }
 
@@ -191,6 +195,23 @@ DEV void block_sum_i64(long long (&v)[CNT], long long (*red)[8], int tid) {
     for (int k = 0; k < CNT; ++k) red[0][k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
   }
   __syncthreads();
+}
+
+// Workgroup of 256: total of field f over `count` rows of `stride` 64-bit
+// signed values starting at base (row r, field f at base[r * stride + f]), as
+// a 128-bit integer in thread 0.  part: 256 __int128 of LDS.
+DEV __int128 block_total_rows(const long long* base, int count, int stride, int f, __int128* part, int tid) {
+  __int128 p = 0;
+  for (int r = tid; r < count; r += 256) p += (__int128)base[(size_t)r * stride + f];
+  part[tid] = p;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if (tid < d) part[tid] += part[tid + d];
+    __syncthreads();
+  }
+  const __int128 t = part[0];
+  __syncthreads();
+  return t;
 }
 
 // Last workgroup of a component to finish (returns true in every thread of
