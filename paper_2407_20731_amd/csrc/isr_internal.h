@@ -189,7 +189,21 @@ hipError_t launch_refsel(const Job& j, int level, int grid_x, hipStream_t s);
 // Streaming path (isr_engine.cuh) for orders 1..7.
 enum FastKind { F_SAMPLE = 0, F_PASSA = 1, F_PASSB = 2 };
 enum DoneSlot { D_SAMPLE = 0, D_GATHER = 1, D_COUNT = 2, D_PASSB = 3, D_REFSEL = 4 };  // D_REFSEL + level
-constexpr int FAST_MAX_ORDER = 7;
+constexpr int FAST_MAX_ORDER = 7;     // every precision
+constexpr int FAST_MAX_ORDER_MF = 11; // FP32 / BF16 (large-order engine, isr_engine_l.cuh)
+inline bool fast_order(int order, int precision) {
+  return order >= 1 && (order <= FAST_MAX_ORDER || (precision != 0 && order <= FAST_MAX_ORDER_MF));
+}
+// tiles of the streaming path: 64 / (N+1)^2 elements each (one from N = 7 up)
+inline long long fast_epw(int order) {
+  const long long n = order + 1;
+  return 64 / (n * n) > 0 ? 64 / (n * n) : 1;
+}
+// values per lane per tile (norm terms of pass A, error terms of pass B)
+inline long long fast_lane_terms(int order) {
+  const long long n = order + 1;
+  return n <= 8 ? 8 : (n * n * n + 63) / 64;
+}
 constexpr int FAST_GMAX = 2048;  // workgroups per component of a streaming pass
 constexpr int GATHER_GMAX = 256;  // workgroups per component of the window-bin gather
 hipError_t launch_fast(int kind, int precision, const Job& j, int grid_x, hipStream_t s);

@@ -2,6 +2,7 @@
 // FP32 transform path.
 #include "isr_batch.cuh"
 #include "isr_engine.cuh"
+#include "isr_engine_l.cuh"
 #include "isr_passes.cuh"
 
 namespace isr {
@@ -21,9 +22,12 @@ size_t batch_lds_fp32() { return batch_lds_prec<P_FP32>(); }
 int batch_resident_fp32(size_t lds) { return batch_resident_prec<P_FP32>(lds); }
 
 hipError_t launch_fast_fp32(int kind, const Job& j, int gx, hipStream_t s) {
+  if (j.order > FAST_MAX_ORDER) return launch_fast_l<P_FP32>(kind, j, gx, s);
   return launch_fast_prec<P_FP32>(kind, j, gx, s);
 }
 
-int resident_fast_fp32(int kind, int order) { return resident_fast_prec<P_FP32>(kind, order); }
+int resident_fast_fp32(int kind, int order) {
+  return order > FAST_MAX_ORDER ? resident_fast_l<P_FP32>(kind, order) : resident_fast_prec<P_FP32>(kind, order);
+}
 
 }  // namespace isr

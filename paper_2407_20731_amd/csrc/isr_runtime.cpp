@@ -303,9 +303,9 @@ Sizes plan_sizes(const isr_field* f) {
   z.zero_bytes = o;
   z.list_cap = z.nv;
   z.off_lists = take((size_t)nc * 2 * z.list_cap * 8);  // list 0, then lists 1 and 2 at half size
-  z.fast = f->order <= FAST_MAX_ORDER;
+  z.fast = fast_order(f->order, f->precision);
   if (z.fast) {
-    const long long epw = 64 / (n * n), ftiles = (f->n_elem + epw - 1) / epw;
+    const long long epw = fast_epw(f->order), ftiles = (f->n_elem + epw - 1) / epw;
     z.sample_stride = std::max<long long>(1, ftiles / 1024);  // about 1024 sampled tiles
     z.off_lidx = take((size_t)nc * z.list_cap * 4);
     z.off_cnt = take((size_t)nc * f->n_elem * 4);
@@ -376,7 +376,7 @@ namespace isr {
 static int enqueue_fast(isr_ctx* c, const Job& j0, const Sizes& z, hipStream_t s, hipEvent_t* ev) {
   Job j = j0;
   const int nc = j.ncomp, prec = j.precision;
-  const long long n = j.order + 1, epw = 64 / (n * n);
+  const long long epw = fast_epw(j.order);
   const long long ftiles = (j.n_elem + epw - 1) / epw;
   auto grid = [&](int kind) {
     const long long slots = (long long)c->num_cu * resident_fast(kind, prec, j.order);
@@ -386,9 +386,9 @@ static int enqueue_fast(isr_ctx* c, const Job& j0, const Sizes& z, hipStream_t s
   };
   j.gA = grid(F_PASSA);
   j.gB = grid(F_PASSB);
-  // terms per lane: 8 slots per tile, tiles per wave
+  // terms per lane: values per lane per tile times tiles per wave
   const long long per_wave = (ftiles + 4ll * std::min(j.gA, j.gB) - 1) / (4ll * std::min(j.gA, j.gB));
-  const long long terms = 8 * per_wave;
+  const long long terms = fast_lane_terms(j.order) * per_wave;
   int h = 1;
   while ((1ll << (h - 1)) < terms) ++h;
   j.xh = std::max(7, std::min(20, h));
@@ -721,6 +721,25 @@ int task_step(Task* t, isr_blob** out) {
 
 // Several snapshots of orders 5, 7 and 9 in ONE persistent launch
 // (isr_batch.cuh); other batches run one after another.
+// Snapshots the persistent kernel does not take run through the request
+// scheduler: up to max_inflight at once on their own streams, so that one
+// snapshot's latency-bound selection kernels overlap another's streaming
+// passes.  Every result equals the snapshot compressed alone.
+static int run_batch_concurrent(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_stats* st) {
+  std::vector<uint64_t> ids(count, 0);
+  std::vector<int> sub(count, ISR_OK);
+  for (int i = 0; i < count; ++i) sub[i] = c->sched->submit(&fs[i], &ids[i]);
+  int first = ISR_OK;
+  for (int i = 0; i < count; ++i) {
+    outs[i] = nullptr;
+    int rc = sub[i];
+    if (rc == ISR_OK) rc = c->sched->poll(ids[i], -1, &outs[i], st ? &st[i] : nullptr);
+    if (st) st[i].status = rc;
+    if (rc != ISR_OK && first == ISR_OK) first = rc;
+  }
+  return first;
+}
+
 int run_batch(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_stats* st) {
   if (count <= 0) return ISR_OK;
   bool persistent = true;
@@ -732,7 +751,7 @@ int run_batch(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_s
     // batches (exact either way) take it
     if (fs[i].precision != ISR_PREC_FP64) persistent = false;
   }
-  if (!persistent) return run_batch_sequential(c, fs, count, outs, st);
+  if (!persistent) return run_batch_concurrent(c, fs, count, outs, st);
   const int prec = fs[0].precision;
   hipStream_t s = (hipStream_t)fs[0].stream;
   const double t_start = now_s();

@@ -305,8 +305,8 @@ hipError_t launch_fast(int kind, int precision, const Job& j, int gx, hipStream_
 }
 
 int resident_fast(int kind, int precision, int order) {
-  static int cache[3][3][8];
-  if (kind < 0 || kind > 2 || precision < 0 || precision > 2 || order < 1 || order > FAST_MAX_ORDER) return 1;
+  static int cache[3][3][16];
+  if (kind < 0 || kind > 2 || precision < 0 || precision > 2 || !fast_order(order, precision)) return 1;
   int& c = cache[kind][precision][order];
   if (c == 0) {
     if (precision == ISR_PREC_FP64)

@@ -48,7 +48,8 @@ def coef_bound(prec, order, u_elem_max):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("order,E,tol", [(7, 512, 1e-3), (5, 300, 1e-3), (9, 100, 1e-3), (3, 77, 1e-2),
-                                         (7, 129, 1e-5), (2, 40, 1e-2), (15, 6, 1e-3)])
+                                         (7, 129, 1e-5), (2, 40, 1e-2), (15, 6, 1e-3), (8, 33, 1e-3),
+                                         (10, 7, 1e-3), (11, 5, 1e-2), (9, 1, 1e-3)])
 def test_mixed_against_oracle(isr_ctx, prec, order, E, tol):
     print(f"[case] prec={prec} order={order} E={E} tol={tol}", flush=True)
     n = order + 1
