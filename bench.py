@@ -93,18 +93,18 @@ def cpu_baseline() -> dict:
                       f"tol 1e-3), full oracle pipeline (FP64 NumPy, one thread), {dt:.1f} s"}
 
 
-def time_single(ctx, u, prec, steps, warmup, stream):
+def time_single(ctx, u, prec, steps, warmup, stream, order=ORDER):
     import numpy as np
     import torch
 
     for _ in range(warmup):
-        ctx.compress(u, ORDER, TOL, prec, stream=stream).free()
+        ctx.compress(u, order, TOL, prec, stream=stream).free()
     torch.cuda.synchronize()
     phases, rels, kept, status = {}, [], [], set()
     blob_bytes = 0
     t0 = time.perf_counter()
     for _ in range(steps):
-        b = ctx.compress(u, ORDER, TOL, prec, stream=stream)
+        b = ctx.compress(u, order, TOL, prec, stream=stream)
         for k, v in b.stats["phase_ms"].items():
             phases.setdefault(k, []).append(v)
         rels.append(max(b.stats["rel_err"]))
@@ -213,6 +213,8 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--order", type=int, default=ORDER, help="order N of the single-snapshot section")
+    ap.add_argument("--elements", type=int, default=E_BENCH, help="elements of the single-snapshot section")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -235,18 +237,19 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": src.numel() * 4, "copies": 3}), flush=True)
         return 0
-    log(f"generating {E_BENCH} elements, N={ORDER}, {NCOMP} components")
-    u = torch.from_numpy(synth.field(E_BENCH, ORDER, ncomp=NCOMP, seed=SEED)).cuda()
+    E, N = args.elements, args.order
+    log(f"generating {E} elements, N={N}, {NCOMP} components")
+    u = torch.from_numpy(synth.field(E, N, ncomp=NCOMP, seed=SEED)).cuda()
     torch.cuda.synchronize()
-    n = ORDER + 1
-    nvals = NCOMP * E_BENCH * n ** 3
+    n = N + 1
+    nvals = NCOMP * E * n ** 3
     stream = torch.cuda.current_stream()
     ctx = isr.Context(device=0, flags=isr.FLAG_TIMING)
     results = {}
     precs = ["bf16", "fp32", "fp64"] if args.precision == "auto" else [args.precision]
     for p in precs:
         steps = args.steps if p != "fp64" or args.precision == "fp64" else max(2, args.steps // 3)
-        results[p] = time_single(ctx, u, p, steps, args.warmup, stream)
+        results[p] = time_single(ctx, u, p, steps, args.warmup, stream, N)
         log(f"{p}: {results[p]['ms']:.3f} ms/step, phases {results[p]['phase_ms']}")
     if args.precision == "auto":
         ok = [p for p in ("bf16", "fp32") if results[p]["status"] == [0] and results[p]["max_rel"] <= TOL]
@@ -266,7 +269,7 @@ def main() -> int:
         byts = nvals * 8 + (r["blob_bytes"] if dom == "pass3" else 0)
         achieved = byts / (avg[dom] / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(head) if dom == "pass3" else None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(head) if dom == "pass3" and (E, N) == (E_BENCH, ORDER) else None,
                 "kernel": KERNEL_NAMES.get(dom, dom), "kernel_ms": avg[dom], "algorithmic_bytes_per_launch": byts}
     # whole-path algorithmic traffic: two field reads plus the blob, per step
     algo = 2 * nvals * 8 + r["blob_bytes"]
@@ -274,9 +277,9 @@ def main() -> int:
         "metric": METRIC, "value": gbs, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r["ms"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": DTYPES[head], "data": "synthetic",
-        "config": {"workload": "single snapshot: 65,536 hex elements, N=7 (8^3 GLL points), 3 FP64 velocity "
-                               "components (805 MB), Fourier-mode generator seed 2, tol 1e-3",
-                   "n_elem": E_BENCH, "order": ORDER, "ncomp": NCOMP, "tol": TOL, "precision": head},
+        "config": {"workload": f"single snapshot: {E:,} hex elements, N={N} ({n}^3 GLL points), 3 FP64 velocity "
+                               f"components ({nvals * 8 / 1e6:.0f} MB), Fourier-mode generator seed 2, tol 1e-3",
+                   "n_elem": E, "order": N, "ncomp": NCOMP, "tol": TOL, "precision": head},
         "roofline": roof,
         "path_hbm_frac": algo / (r["ms"] / 1e3) / 1e9 / HBM_PEAK_GBS,
         "phase_ms": avg,
