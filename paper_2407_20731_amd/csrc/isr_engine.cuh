@@ -5,12 +5,12 @@
 //   k_sample  every sample_stride-th tile: rounded exponent histogram of the
 //             energies and rounded U2, which place a window of three energy
 //             exponent bins around the expected threshold
-//   k_passA   exact norm sum, exact sum of the energies below the window,
-//             window energies (with their element) to list 0, per-element
-//             count of energies above the window
+//   k_passA   exact norm sum, sum of the energies below the window, window
+//             energies (with their element) to list 0, per-element count of
+//             energies above the window
 //   k_passB   keep e >= tau, bitmaps, kept values at per-element offsets
-//             (known up front: no look-back), inverse of the kept set, exact
-//             error sum; the last workgroup of a component finalizes it
+//             (known up front: no look-back), inverse of the kept set, error
+//             sum; the last workgroup of a component finalizes it
 //
 // Exact sums without atomics: every lane splits each non-negative term x <= M
 // into three parts on fixed grids (error-free extraction against fixed powers
@@ -19,6 +19,11 @@
 // sums that stay exact; the rare term that leaves a remainder (far below M or
 // above M) goes to the global exponent bins instead.  Workgroups publish
 // their three integer sums; the consumer turns the totals into exact bins.
+// The norm sum is exact on every path, so U2 is that of the FP64 field.  The
+// FP64 path sums the energies and the error terms the same way; the MFMA
+// paths, whose energies already carry the transform error, add them in a
+// fixed order per lane instead (one FP64 add a term) and split only each
+// lane's total on the grids, so their results stay deterministic.
 //
 // Transforms on MFMA use a block-diagonal trick for n <= 8: a 16x16 tile
 // holds two 8x8 copies of the 1D matrix, the K dimension pairs the contracted
@@ -528,6 +533,7 @@ template <int N, int PREC>
 __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passA(Job j) {
   typedef Eng<N, PREC> G;
   constexpr int n3 = G::n3, NS = G::NS, EPW = G::EPW;
+  constexpr bool EXACT = PREC == P_FP64;
   __shared__ PassALds<N, PREC> L;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int comp = blockIdx.y;
@@ -547,6 +553,7 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passA(Job j) {
   tab_load<G>(L.tab, j.tab, tid);
   __syncthreads();
   XAcc an = {0.0, 0.0, 0.0}, ae = {0.0, 0.0, 0.0};
+  double pe = 0.0;  // fixed-order sum of the energies below the window
   u64 hi_tot = 0ull;
   u32 ncap = 0u;
   const double* ub = j.u + (size_t)comp * j.comp_stride;
@@ -591,9 +598,14 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passA(Job j) {
       const int ex = bits_exp(key);
       const bool hi = v && ex >= whi;
       const bool cp = v && ex < whi && ex >= wlo;
-      double r = xadd_r(ae, PE, (v && ex < wlo) ? en : 0.0);
-      if (hi && ex == HBINS - 1) r = en;  // Inf/NaN: counted in the flag bin
-      if (r != 0.0) slow_bin(gE, r);
+      if constexpr (EXACT) {
+        double r = xadd_r(ae, PE, (v && ex < wlo) ? en : 0.0);
+        if (hi && ex == HBINS - 1) r = en;  // Inf/NaN: counted in the flag bin
+        if (r != 0.0) slow_bin(gE, r);
+      } else {
+        pe += (v && ex < wlo) ? en : 0.0;
+        if (hi && ex == HBINS - 1) slow_bin(gE, en);
+      }
       __builtin_amdgcn_sched_barrier(0);
       const u64 bh = ballot(hi);
       hc += (u32)__popcll(bh);
@@ -622,6 +634,10 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passA(Job j) {
   }
   asm volatile("" ::: "memory");
   cap_flush(L.key[wv], L.idx[wv], ncap, st, list, lidx, j.list_cap, lane);
+  if constexpr (!EXACT) {
+    const double r = xadd_sum(ae, PE, pe);
+    if (r != 0.0) slow_bin(gE, r);
+  }
   long long v[7];
   long long kn[3], ke[3];
   xints(an, PN, kn);
@@ -653,6 +669,7 @@ template <int N, int PREC>
 __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passB(Job j) {
   typedef Eng<N, PREC> G;
   constexpr int n3 = G::n3, NS = G::NS, EPW = G::EPW, W = G::W;
+  constexpr bool EXACT = PREC == P_FP64;
   static_assert(EPW * W <= 16, "tile bitmap fits the LDS slot");
   __shared__ PassBLds<N, PREC> L;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -673,6 +690,7 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passB(Job j) {
   tab_load<G>(L.tab, j.tab, tid);
   __syncthreads();
   XAcc ar = {0.0, 0.0, 0.0};
+  double pr = 0.0;  // fixed-order sum of the error terms
   bool bad = false;
   const double* ub = j.u + (size_t)comp * j.comp_stride;
   const bool vec = ((((uintptr_t)ub) & 15) == 0);
@@ -814,13 +832,21 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passB(Job j) {
     for (int s = 0; s < NS; ++s) {
       const double d = u[s] - ut[s];
       const double x = G::valid(s, lane, ne) ? jw(j.jac, e0 + G::elem(s, lane), L.tab.w3[s][lane]) * (d * d) : 0.0;
-      const double r = xadd_r(ar, PR, x);
-      if (r != 0.0) slow_bin(gR, r);
-      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (EXACT) {
+        const double r = xadd_r(ar, PR, x);
+        if (r != 0.0) slow_bin(gR, r);
+        __builtin_amdgcn_sched_barrier(0);
+      } else {
+        pr += x;
+      }
     }
   }
   if (ballot(bad)) {
     if (lane == 0) atomicOr(&st->flags, ST_LIST);
+  }
+  if constexpr (!EXACT) {
+    const double r = xadd_sum(ar, PR, pr);
+    if (r != 0.0) slow_bin(gR, r);
   }
   long long v[3];
   xints(ar, PR, v);

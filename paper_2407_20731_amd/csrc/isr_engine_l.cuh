@@ -280,6 +280,7 @@ __global__ __launch_bounds__(256, 2) void k_passAL(Job j) {
   tabl_load(L.tab, j.tab, tid);
   __syncthreads();
   XAcc an = {0.0, 0.0, 0.0}, ae = {0.0, 0.0, 0.0};
+  double pe = 0.0;  // fixed-order sum of the energies below the window
   u64 hi_tot = 0ull;
   u32 ncap = 0u;
   const double* ub = j.u + (size_t)comp * j.comp_stride;
@@ -307,9 +308,8 @@ __global__ __launch_bounds__(256, 2) void k_passAL(Job j) {
         const int ex = bits_exp(key);
         const bool hi = v && ex >= whi;
         const bool cp = v && ex < whi && ex >= wlo;
-        double r = xadd_r(ae, PE, (v && ex < wlo) ? en : 0.0);
-        if (hi && ex == HBINS - 1) r = en;
-        if (r != 0.0) slow_bin(gE, r);
+        pe += (v && ex < wlo) ? en : 0.0;
+        if (hi && ex == HBINS - 1) slow_bin(gE, en);  // Inf/NaN: counted in the flag bin
         hc += (u32)__popcll(ballot(hi));
         const u64 bc = ballot(cp);
         if (bc) {
@@ -331,6 +331,10 @@ __global__ __launch_bounds__(256, 2) void k_passAL(Job j) {
   }
   asm volatile("" ::: "memory");
   cap_flush(L.key[wv], L.idx[wv], ncap, st, list, lidx, j.list_cap, lane);
+  {
+    const double r = xadd_sum(ae, PE, pe);
+    if (r != 0.0) slow_bin(gE, r);
+  }
   long long v[7];
   long long kn[3], ke[3];
   xints(an, PN, kn);
@@ -381,6 +385,7 @@ __global__ __launch_bounds__(256, 2) void k_passBL(Job j) {
   tabl_load(L.tab, j.tab, tid);
   __syncthreads();
   XAcc ar = {0.0, 0.0, 0.0};
+  double pr = 0.0;  // fixed-order sum of the error terms
   bool bad = false;
   const double* ub = j.u + (size_t)comp * j.comp_stride;
   const long long nw = (long long)gridDim.x * 4;
@@ -463,7 +468,7 @@ __global__ __launch_bounds__(256, 2) void k_passBL(Job j) {
         ((float*)j.values)[pos] = val;
     }
     G::template stage<2>(buf, mt.fv, mt.hv, mt.lv, lane);
-    // last inverse stage and the exact error terms (field values reloaded)
+    // last inverse stage and the error terms (field values reloaded)
 #pragma unroll 1
     for (int b = 0; b < G::NB; ++b) {
       float x[4], y[4];
@@ -476,14 +481,17 @@ __global__ __launch_bounds__(256, 2) void k_passBL(Job j) {
         const double u = v ? tile[q] : 0.0;
         const double d = u - (double)y[m];
         const double xv = v ? (j.jac ? jac * L.tab.w3[q] : L.tab.w3[q]) * (d * d) : 0.0;
-        const double r = xadd_r(ar, PR, xv);
-        if (r != 0.0) slow_bin(gR, r);
+        pr += xv;
       }
     }
     asm volatile("" ::: "memory");
   }
   if (ballot(bad)) {
     if (lane == 0) atomicOr(&st->flags, ST_LIST);
+  }
+  {
+    const double r = xadd_sum(ar, PR, pr);
+    if (r != 0.0) slow_bin(gR, r);
   }
   long long v[3];
   xints(ar, PR, v);

@@ -5,6 +5,7 @@
 // does not exceed B = (tol*tol)*U2.
 #pragma once
 
+#include "isr.h"
 #include "isr_common.cuh"
 
 namespace isr {
@@ -52,6 +53,13 @@ DEV void select1_body(const Job& j, int comp, int sample) {
     return;
   }
   double B = (tol * tol) * U2;
+  // MFMA paths: the measured error differs from the dropped energy by the
+  // transform error (about 1e-5 relative in FP32-split BF16 at tol 1e-3), so
+  // they select against a budget that much smaller and rarely need a repair
+  if (j.precision == ISR_PREC_BF16)
+    B = B * (1.0 - 0x1p-10);
+  else if (j.precision == ISR_PREC_FP32)
+    B = B * (1.0 - 0x1p-17);
   if (!sample && comp < 8 && j.Bov[comp] >= 0.0) B = j.Bov[comp];
   // Tint = X(B) + half ulp(B) - (sig(B) odd)
   const u64 bb = dbits(B);

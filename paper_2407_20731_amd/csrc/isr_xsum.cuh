@@ -77,6 +77,25 @@ DEV double xadd_r(XAcc& A, const XParm& P, double x) {
   return in ? r2 - q3 : x;
 }
 
+// A lane's fixed-order FP64 sum s of at most 2^(h-1) terms in [0, M] (so
+// s <= 2^(m+h-1)) added to the three sums, exactly down to u3; returns what
+// is left for the global bins: the part below u3 (0 <= r < 2 u3), or s itself
+// when it is out of that range (Inf and NaN included).
+DEV double xadd_sum(XAcc& A, const XParm& P, double s) {
+  const bool in = s >= 0.0 && s <= 0.5 * P.S1;
+  const double y = in ? s : 0.0;
+  const double q1 = (P.S1 + y) - P.S1;
+  const double r1 = y - q1;
+  const double q2 = (P.S2 + r1) - P.S2;
+  const double r2 = r1 - q2;
+  const double t3 = (P.S3 + r2) - P.S3;
+  const double q3 = t3 > r2 ? t3 - P.u3 : t3;
+  A.a1 = A.a1 + q1;
+  A.a2 = A.a2 + q2;
+  A.a3 = A.a3 + q3;
+  return in ? r2 - q3 : s;
+}
+
 // x = q1 + q2 + q3 + r3: q_k on the grid of u_k (|q1| <= M, |q2| <= u1,
 // |q3| <= u2), the last part rounded down so that 0 <= r3 < 2 u3.
 DEV void xadd(XAcc& A, const XParm& P, double x, HistBin* g) {
