@@ -23,6 +23,7 @@ Output: ONE JSON line.
 from __future__ import annotations
 
 import argparse
+import tempfile
 import json
 import math
 import os
@@ -150,7 +151,7 @@ def run_batch(ctx, pool, prec):
             "precision": prec, "all_ok": ok, "max_rel_err": rel}
 
 
-def run_serving(pool, prec, budget, n_req, rate_frac):
+def run_serving(pool, prec, budget, n_req, rate_frac, tune_path=None):
     """Config 5: Poisson arrivals, E lognormal (median 20k, sigma 1, clip
     1k-500k), N uniform in {5,7,9}, continuous batching under an HBM budget."""
     import numpy as np
@@ -165,7 +166,7 @@ def run_serving(pool, prec, budget, n_req, rate_frac):
         E = int(np.clip(round(math.exp(rng.normal(math.log(20000), 1.0))), 1000, 500000))
         off = int(rng.integers(0, pool[N].shape[1] - E + 1))
         reqs.append((N, off, E))
-    with isr.Context(device=0, budget_bytes=budget, max_inflight=8) as ctx:
+    with isr.Context(device=0, budget_bytes=budget, max_inflight=8, autotune_path=tune_path) as ctx:
         def submit(r):
             N, off, E = r
             return ctx.submit(pool[N][:, off:off + E], N, TOL, prec)
@@ -215,6 +216,10 @@ def main() -> int:
     ap.add_argument("--serving-requests", type=int, default=400)
     ap.add_argument("--order", type=int, default=ORDER, help="order N of the single-snapshot section")
     ap.add_argument("--elements", type=int, default=E_BENCH, help="elements of the single-snapshot section")
+    ap.add_argument("--tile", type=int, default=None,
+                    help="tile shape of the single-snapshot section (0: wave-tile engine, T: dense tiles); "
+                         "default: chosen by the autotuner")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in tile shapes (no autotuning)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -244,9 +249,19 @@ def main() -> int:
     n = N + 1
     nvals = NCOMP * E * n ** 3
     stream = torch.cuda.current_stream()
-    ctx = isr.Context(device=0, flags=isr.FLAG_TIMING)
+    tune_path = os.path.join(tempfile.mkdtemp(prefix="isr_tiles_"), "tiles.txt")
+    ctx = isr.Context(device=0, flags=isr.FLAG_TIMING, autotune_path=tune_path)
     results = {}
     precs = ["bf16", "fp32", "fp64"] if args.precision == "auto" else [args.precision]
+    tuning = {}
+    for p in precs:
+        if p == "fp64":
+            continue
+        if args.tile is not None:
+            ctx.set_tile(N, p, args.tile)
+        elif not args.no_tune:
+            tuning[p] = ctx.autotune(u, N, TOL, p, reps=2)
+            log(f"autotune N={N} {p}: {tuning[p]}")
     for p in precs:
         steps = args.steps if p != "fp64" or args.precision == "fp64" else max(2, args.steps // 3)
         results[p] = time_single(ctx, u, p, steps, args.warmup, stream, N)
@@ -281,6 +296,8 @@ def main() -> int:
                                f"components ({nvals * 8 / 1e6:.0f} MB), Fourier-mode generator seed 2, tol 1e-3",
                    "n_elem": E, "order": N, "ncomp": NCOMP, "tol": TOL, "precision": head},
         "roofline": roof,
+        "tile": {p: ctx.get_tile(N, p) for p in precs if p != "fp64"},
+        "autotune": tuning,
         "path_hbm_frac": algo / (r["ms"] / 1e3) / 1e9 / HBM_PEAK_GBS,
         "phase_ms": avg,
         "max_rel_err": r["max_rel"], "kept_fraction": r["kept"] / nvals, "status": r["status"],
@@ -295,12 +312,21 @@ def main() -> int:
         log("generating element pools on the device (500k elements per order)")
         pool = pools((5, 7, 9), 500000)
         torch.cuda.synchronize()
+        if not args.no_tune:
+            # tile shapes of the batch / serving orders, tuned on 50k-element
+            # windows of the pools (the mean request size of the batch mix)
+            with isr.Context(device=0, autotune_path=tune_path) as tctx:
+                for p in sorted({head, "fp32"} - {"fp64"}):
+                    for NN in (5, 7, 9):
+                        rep = tctx.autotune(pool[NN][:, :50000], NN, TOL, p, reps=2)
+                        out.setdefault("autotune_mix", {})[f"N{NN}_{p}"] = rep
+                        log(f"autotune N={NN} {p} (50k elements): {rep}")
         if not args.no_batch:
-            with isr.Context(device=0, budget_bytes=128 << 30) as bctx:
+            with isr.Context(device=0, budget_bytes=128 << 30, autotune_path=tune_path) as bctx:
                 out["batch"] = run_batch(bctx, pool, head)
                 log(f"batch: {out['batch']}")
         if not args.no_serving:
-            out["serving"] = run_serving(pool, "fp32", 64 << 30, args.serving_requests, 0.7)
+            out["serving"] = run_serving(pool, "fp32", 64 << 30, args.serving_requests, 0.7, tune_path)
             log(f"serving: {out['serving']}")
         del pool
     if not args.no_cpu:

@@ -80,7 +80,8 @@ typedef struct {
   uint64_t hbm_budget_bytes; /* cap on device memory the library holds; 0 = 64 GiB */
   int32_t max_inflight;      /* isr_submit: requests resident at once; 0 = 8 */
   int32_t reserved;
-  const char *autotune_path; /* optional tile table written by the autotuner; NULL = built in */
+  const char *autotune_path; /* optional tile-shape table: read at create when
+                                present, written by isr_autotune; NULL = none */
 } isr_config;
 
 /* One snapshot to compress.
@@ -213,6 +214,40 @@ int isr_blob_size(const isr_blob *b, uint64_t *bytes);
 int isr_blob_to_host(const isr_blob *b, void *buf, uint64_t cap);
 int isr_blob_from_host(isr_ctx *ctx, const void *buf, uint64_t n, isr_blob **out);
 void isr_blob_free(isr_blob *b);
+
+/* ---- tile shapes and the autotuner --------------------------------------
+ * The FP32 / BF16 streaming passes come in several tile shapes per order.
+ * Shape 0 is the wave-tile engine: a wavefront owns 64 / (N+1)^2 elements
+ * (one from N = 7 up) and works in the MFMA register layout.  Shape T > 0 is
+ * the dense-tile engine: a wavefront owns T consecutive elements and does all
+ * per-value work (norm, energies, window tests, keep decisions, bitmaps,
+ * ranks, error terms) in dense order.  Every shape meets the same bound and
+ * passes the same checks; the choice only changes speed.  The table starts
+ * from the built-in choice, or from config.autotune_path when that file
+ * exists (text lines "order precision tile"). */
+typedef struct {
+  int32_t count;     /* candidates timed */
+  int32_t tile[16];  /* their shapes */
+  double ms[16];     /* best wall-clock milliseconds of one compression each */
+  int32_t best;      /* shape now in the table */
+} isr_tune_report;
+
+/* Shape in use for (order, precision).  Errors: ISR_EINVAL. */
+int isr_get_tile(isr_ctx *ctx, int32_t order, int32_t precision, int32_t *tile);
+
+/* Use shape `tile` for (order, precision) from the next request on: a
+ * compiled shape, 0, or -1 for the built-in choice.  Requests already
+ * admitted keep theirs.  Errors: ISR_EINVAL (FP64, an order without a
+ * streaming path, a shape that is not compiled). */
+int isr_set_tile(isr_ctx *ctx, int32_t order, int32_t precision, int32_t tile);
+
+/* Autotuner: compress f with every candidate shape of (f->order,
+ * f->precision), one warm-up call and then the best of `reps` timed calls
+ * each, keep the fastest in the table and, when config.autotune_path was
+ * given, rewrite that file with the whole table.  f should look like the
+ * production snapshots (its size matters).  rep may be NULL.  Errors: as
+ * isr_compress; ISR_EINVAL for FP64 (it has one shape). */
+int isr_autotune(isr_ctx *ctx, const isr_field *f, int32_t reps, isr_tune_report *rep);
 
 /* Host-only: the library's own FP64 tables for order N (each entry the
  * correctly rounded value of the exact quantity): xi[n], w[n], V[n*n]

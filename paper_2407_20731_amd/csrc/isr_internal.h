@@ -124,6 +124,7 @@ struct Job {
   long long nchunk;
   int gA, gB;          // workgroups per component of the two streaming passes
   int xh;              // extraction headroom (log2 of twice the terms per lane)
+  int tile;            // elements per wavefront tile of the dense-tile engine; 0 = wave-tile engine
   u64* lookback;       // [ncomp][tiles]
   u32* ticket;         // [4]
   // blob (device)
@@ -194,20 +195,56 @@ constexpr int FAST_MAX_ORDER_MF = 11; // FP32 / BF16 (large-order engine, isr_en
 inline bool fast_order(int order, int precision) {
   return order >= 1 && (order <= FAST_MAX_ORDER || (precision != 0 && order <= FAST_MAX_ORDER_MF));
 }
-// tiles of the streaming path: 64 / (N+1)^2 elements each (one from N = 7 up)
-inline long long fast_epw(int order) {
+// Tile shapes compiled for the dense-tile engine (isr_engine_d.cuh, FP32 and
+// BF16): X(order, elements per wavefront tile).
+#define ISR_DENSE_SHAPES(X)                                                                               \
+  X(1, 32) X(1, 64) X(2, 16) X(2, 32) X(3, 4) X(3, 8) X(4, 4) X(4, 8) X(5, 2) X(5, 4) X(5, 8) X(6, 1) X(6, 2) \
+  X(6, 3) X(7, 1) X(7, 2) X(8, 1) X(8, 2) X(9, 1) X(9, 2) X(10, 1) X(11, 1)
+inline bool dense_shape(int order, int tile) {
+#define ISR_SHAPE_IS(O, T) \
+  if (order == O && tile == T) return true;
+  ISR_DENSE_SHAPES(ISR_SHAPE_IS)
+#undef ISR_SHAPE_IS
+  return false;
+}
+// candidate tiles of one order for the autotuner: 0 (the wave-tile engine,
+// orders 1..11) first, then the compiled dense shapes; returns the count
+inline int tile_candidates(int order, int* out, int cap) {
+  int k = 0;
+  if (order >= 1 && order <= FAST_MAX_ORDER_MF && k < cap) out[k++] = 0;
+#define ISR_SHAPE_ADD(O, T) \
+  if (order == O && k < cap) out[k++] = T;
+  ISR_DENSE_SHAPES(ISR_SHAPE_ADD)
+#undef ISR_SHAPE_ADD
+  return k;
+}
+// built-in choice before any tuning (measured on MI355X, BF16, tol 1e-3)
+inline int default_tile(int order, int precision) {
+  if (precision == 0 || order < 1 || order > FAST_MAX_ORDER_MF) return 0;
+  static const int t[12] = {0, 32, 16, 8, 4, 4, 2, 0, 1, 1, 1, 1};
+  return t[order];
+}
+// elements per tile of the streaming path: the dense tile, else 64 / (N+1)^2
+// (one from N = 7 up)
+inline long long fast_epw(int order, int tile) {
+  if (tile > 0) return tile;
   const long long n = order + 1;
   return 64 / (n * n) > 0 ? 64 / (n * n) : 1;
 }
 // values per lane per tile (norm terms of pass A, error terms of pass B)
-inline long long fast_lane_terms(int order) {
+inline long long fast_lane_terms(int order, int tile) {
   const long long n = order + 1;
+  if (tile > 0) return (tile * n * n * n + 63) / 64;
   return n <= 8 ? 8 : (n * n * n + 63) / 64;
 }
 constexpr int FAST_GMAX = 2048;  // workgroups per component of a streaming pass
 constexpr int GATHER_GMAX = 256;  // workgroups per component of the window-bin gather
 hipError_t launch_fast(int kind, int precision, const Job& j, int grid_x, hipStream_t s);
-int resident_fast(int kind, int precision, int order);
+int resident_fast(int kind, int precision, int order, int tile);
+hipError_t launch_dense_fp32(int kind, const Job& j, int grid_x, hipStream_t s);
+hipError_t launch_dense_bf16(int kind, const Job& j, int grid_x, hipStream_t s);
+int resident_dense_fp32(int kind, int order, int tile);
+int resident_dense_bf16(int kind, int order, int tile);
 hipError_t launch_fast_fp64(int kind, const Job& j, int grid_x, hipStream_t s);
 hipError_t launch_fast_fp32(int kind, const Job& j, int grid_x, hipStream_t s);
 hipError_t launch_fast_bf16(int kind, const Job& j, int grid_x, hipStream_t s);

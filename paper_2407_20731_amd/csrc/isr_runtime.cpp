@@ -201,6 +201,8 @@ struct isr_ctx {
   std::mutex mu;  // serialises device pipelines
   std::unique_ptr<isr::Scheduler> sched;
   int max_inflight = 8;
+  std::atomic<int> tile[ISR_MAX_ORDER + 1][3];  // tile shape per (order, precision); -1 = built-in
+  std::string tune_path;           // tile table file (read at create, written by the autotuner)
   CompState* st_host = nullptr;  // pinned
   std::mutex host_mu;            // pool of pinned per-request state buffers
   std::vector<CompState*> host_all, host_free;
@@ -274,7 +276,7 @@ static int check_field(const isr_field* f) {
 
 namespace isr {
 
-Sizes plan_sizes(const isr_field* f) {
+Sizes plan_sizes(const isr_field* f, int tile) {
   Sizes z;
   const long long n = f->order + 1, n3 = n * n * n;
   const int nc = f->ncomp;
@@ -304,8 +306,9 @@ Sizes plan_sizes(const isr_field* f) {
   z.list_cap = z.nv;
   z.off_lists = take((size_t)nc * 2 * z.list_cap * 8);  // list 0, then lists 1 and 2 at half size
   z.fast = fast_order(f->order, f->precision);
+  z.tile = z.fast && f->precision != ISR_PREC_FP64 && dense_shape(f->order, tile) ? tile : 0;
   if (z.fast) {
-    const long long epw = fast_epw(f->order), ftiles = (f->n_elem + epw - 1) / epw;
+    const long long epw = fast_epw(f->order, z.tile), ftiles = (f->n_elem + epw - 1) / epw;
     z.sample_stride = std::max<long long>(1, ftiles / 1024);  // about 1024 sampled tiles
     z.off_lidx = take((size_t)nc * z.list_cap * 4);
     z.off_cnt = take((size_t)nc * f->n_elem * 4);
@@ -349,6 +352,7 @@ static Job make_job(isr_ctx* c, const isr_field* f, const Sizes& z, char* scratc
   j.lists = (u64*)(scratch + z.off_lists);
   j.list_cap = z.list_cap;
   j.done = (u32*)(scratch + z.off_done);
+  j.tile = z.tile;
   if (z.fast) {
     j.lidx = (u32*)(scratch + z.off_lidx);
     j.cnt = (u32*)(scratch + z.off_cnt);
@@ -376,10 +380,10 @@ namespace isr {
 static int enqueue_fast(isr_ctx* c, const Job& j0, const Sizes& z, hipStream_t s, hipEvent_t* ev) {
   Job j = j0;
   const int nc = j.ncomp, prec = j.precision;
-  const long long epw = fast_epw(j.order);
+  const long long epw = fast_epw(j.order, j.tile);
   const long long ftiles = (j.n_elem + epw - 1) / epw;
   auto grid = [&](int kind) {
-    const long long slots = (long long)c->num_cu * resident_fast(kind, prec, j.order);
+    const long long slots = (long long)c->num_cu * resident_fast(kind, prec, j.order, j.tile);
     long long g = std::max<long long>(1, slots / nc);
     g = std::min<long long>(g, (ftiles + 3) / 4);
     return (int)std::max<long long>(1, std::min<long long>(g, FAST_GMAX));
@@ -388,7 +392,7 @@ static int enqueue_fast(isr_ctx* c, const Job& j0, const Sizes& z, hipStream_t s
   j.gB = grid(F_PASSB);
   // terms per lane: values per lane per tile times tiles per wave
   const long long per_wave = (ftiles + 4ll * std::min(j.gA, j.gB) - 1) / (4ll * std::min(j.gA, j.gB));
-  const long long terms = fast_lane_terms(j.order) * per_wave;
+  const long long terms = fast_lane_terms(j.order, j.tile) * per_wave;
   int h = 1;
   while ((1ll << (h - 1)) < terms) ++h;
   j.xh = std::max(7, std::min(20, h));
@@ -532,9 +536,15 @@ int ctx_device(const isr_ctx* c) { return c->device; }
 int ctx_max_inflight(const isr_ctx* c) { return c->max_inflight; }
 uint64_t ctx_budget(const isr_ctx* c) { return c->arena->budget(); }
 
+int ctx_tile(const isr_ctx* c, int order, int precision) {
+  if (precision < ISR_PREC_FP32 || precision > ISR_PREC_BF16 || order < 1 || order > ISR_MAX_ORDER) return 0;
+  const int t = c->tile[order][precision].load();
+  return t >= 0 ? t : default_tile(order, precision);
+}
+
 // Footprint a request needs from the arena (scratch + worst-case blob).
 uint64_t request_footprint(const isr_field* f) {
-  Sizes z = plan_sizes(f);
+  Sizes z = plan_sizes(f, 0);
   return (uint64_t)z.scratch_bytes + z.blob_max + 512;
 }
 
@@ -594,7 +604,7 @@ int task_begin(isr_ctx* c, const isr_field* f, hipStream_t s, bool timing, Task*
   t->f = *f;
   t->s = s;
   t->t_start = now_s();
-  t->z = plan_sizes(f);
+  t->z = plan_sizes(f, ctx_tile(c, f->order, f->precision));
   t->scratch = (char*)c->arena->alloc(t->z.scratch_bytes);
   if (!t->scratch) return fail(ISR_ENOMEM, "scratch of %zu bytes does not fit the HBM budget", t->z.scratch_bytes);
   t->b = new_blob(c, f, t->z);
@@ -777,7 +787,7 @@ int run_batch(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_s
   for (int i = 0; i < count; ++i) {
     outs[i] = nullptr;
     Snap& x = sn[i];
-    x.z = plan_sizes(&fs[i]);
+    x.z = plan_sizes(&fs[i], 0);
     x.z.sample_stride = x.z.tiles >= 1024 ? 32 : 0;  // the batch kernel runs the general passes
     x.scratch = (char*)c->arena->alloc(x.z.scratch_bytes);
     x.b = x.scratch ? new_blob(c, &fs[i], x.z) : nullptr;
@@ -953,6 +963,29 @@ int run_compress(isr_ctx* c, const isr_field* f, isr_blob** out, isr_stats* st) 
 
 }  // namespace isr
 
+// Tile-shape table file: one "order precision tile" line per tuned entry.
+static void read_tile_table(isr_ctx* c) {
+  FILE* fp = std::fopen(c->tune_path.c_str(), "r");
+  if (!fp) return;  // not written yet
+  int o, p, t;
+  while (std::fscanf(fp, "%d %d %d", &o, &p, &t) == 3)
+    if (o >= 1 && o <= ISR_MAX_ORDER && p >= ISR_PREC_FP32 && p <= ISR_PREC_BF16 && fast_order(o, p) &&
+        (t == 0 || dense_shape(o, t)))
+      c->tile[o][p] = t;
+  std::fclose(fp);
+}
+
+static int write_tile_table(isr_ctx* c) {
+  const std::string tmp = c->tune_path + ".tmp";
+  FILE* fp = std::fopen(tmp.c_str(), "w");
+  if (!fp) return fail(ISR_EINVAL, "cannot write the tile table %s", tmp.c_str());
+  for (int o = 1; o <= ISR_MAX_ORDER; ++o)
+    for (int p = ISR_PREC_FP32; p <= ISR_PREC_BF16; ++p)
+      if (c->tile[o][p].load() >= 0) std::fprintf(fp, "%d %d %d\n", o, p, c->tile[o][p].load());
+  const bool ok = std::fclose(fp) == 0 && std::rename(tmp.c_str(), c->tune_path.c_str()) == 0;
+  return ok ? ISR_OK : fail(ISR_EINVAL, "cannot write the tile table %s", c->tune_path.c_str());
+}
+
 // ---------------------------------------------------------------------------
 // C ABI
 
@@ -980,6 +1013,12 @@ int isr_create(const isr_config* cfg, isr_ctx** out) {
   HIPCHK(hipGetDeviceProperties(&prop, c->device));
   c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   c->arena.reset(new isr::Arena(d.hbm_budget_bytes ? d.hbm_budget_bytes : (64ull << 30)));
+  for (auto& row : c->tile)
+    for (auto& t : row) t = -1;
+  if (d.autotune_path) {
+    c->tune_path = d.autotune_path;
+    read_tile_table(c.get());
+  }
   int rc = upload_tables(c.get());
   if (rc) return rc;
   HIPCHK(hipHostMalloc((void**)&c->st_host, sizeof(CompState) * ISR_MAX_COMP * 64, hipHostMallocDefault));
@@ -1025,6 +1064,74 @@ int isr_compress_batch(isr_ctx* c, const isr_field* fs, int32_t count, isr_blob*
   }
   std::lock_guard<std::mutex> g(c->mu);
   return isr::run_batch(c, fs, count, outs, st);
+}
+
+int isr_get_tile(isr_ctx* c, int32_t order, int32_t precision, int32_t* tile) {
+  if (!c || !tile) return fail(ISR_EINVAL, "ctx or tile is NULL");
+  if (order < 1 || order > ISR_MAX_ORDER || precision < ISR_PREC_FP64 || precision > ISR_PREC_BF16)
+    return fail(ISR_EINVAL, "bad order %d or precision %d", order, precision);
+  *tile = ctx_tile(c, order, precision);
+  return ISR_OK;
+}
+
+int isr_set_tile(isr_ctx* c, int32_t order, int32_t precision, int32_t tile) {
+  if (!c) return fail(ISR_EINVAL, "ctx is NULL");
+  if (precision != ISR_PREC_FP32 && precision != ISR_PREC_BF16)
+    return fail(ISR_EINVAL, "tile shapes exist for FP32 and BF16 only");
+  if (order < 1 || order > ISR_MAX_ORDER || !fast_order(order, precision))
+    return fail(ISR_EINVAL, "order %d has no streaming path", order);
+  if (tile != -1 && tile != 0 && !dense_shape(order, tile))
+    return fail(ISR_EINVAL, "tile shape %d is not compiled for order %d", tile, order);
+  c->tile[order][precision] = tile;
+  return ISR_OK;
+}
+
+int isr_autotune(isr_ctx* c, const isr_field* f, int32_t reps, isr_tune_report* rep) {
+  if (!c) return fail(ISR_EINVAL, "ctx is NULL");
+  int rc = check_field(f);
+  if (rc) return rc;
+  if (f->precision == ISR_PREC_FP64 || !fast_order(f->order, f->precision))
+    return fail(ISR_EINVAL, "nothing to tune for order %d precision %d", f->order, f->precision);
+  rc = set_device(c);
+  if (rc) return rc;
+  int cand[16];
+  const int nc = tile_candidates(f->order, cand, 16);
+  const int before = c->tile[f->order][f->precision].load();
+  double best_ms = 0.0;
+  int best = -1;
+  isr_tune_report r;
+  std::memset(&r, 0, sizeof(r));
+  for (int k = 0; k < nc; ++k) {
+    c->tile[f->order][f->precision] = cand[k];
+    double ms = 0.0;
+    for (int it = 0; it <= std::max(1, (int)reps); ++it) {
+      isr_blob* b = nullptr;
+      const double t0 = now_s();
+      {
+        std::lock_guard<std::mutex> g(c->mu);
+        rc = run_compress(c, f, &b, nullptr);
+      }
+      const double dt = (now_s() - t0) * 1e3;
+      if (b) isr_blob_free(b);
+      if (rc != ISR_OK && rc != ISR_ETOL) {
+        c->tile[f->order][f->precision] = before;
+        return rc;
+      }
+      if (it > 0) ms = it == 1 ? dt : std::min(ms, dt);  // the first call warms up
+    }
+    r.tile[k] = cand[k];
+    r.ms[k] = ms;
+    if (best < 0 || ms < best_ms) {
+      best_ms = ms;
+      best = cand[k];
+    }
+  }
+  r.count = nc;
+  r.best = best;
+  c->tile[f->order][f->precision] = best;
+  if (rep) *rep = r;
+  if (!c->tune_path.empty()) return write_tile_table(c);
+  return ISR_OK;
 }
 
 int isr_submit(isr_ctx* c, const isr_field* f, uint64_t* req) {

@@ -57,7 +57,8 @@ struct Sizes {
   size_t off_histE = 0, off_histN = 0, off_histR = 0, off_histL = 0, off_st = 0, off_ticket = 0,
          off_lookback = 0, off_lists = 0, off_histEs = 0, off_histNs = 0, off_done = 0, off_lidx = 0, off_cnt = 0,
          off_slotsA = 0, off_slotsB = 0, off_chunk = 0, off_gslot = 0;
-  bool fast = false;         // streaming path (orders 1..7)
+  bool fast = false;         // streaming path
+  int tile = 0;              // its dense-tile shape (elements per wavefront tile); 0 = wave-tile engine
   int gA = 0, gB = 0, xh = 0;  // its grids (workgroups per component) and extraction headroom
   long long sample_stride = 0;
   size_t zero_bytes = 0;     // leading scratch bytes to clear
@@ -65,7 +66,8 @@ struct Sizes {
   size_t scratch_bytes = 0;
   size_t blob_max = 0;       // worst-case blob allocation
 };
-Sizes plan_sizes(const isr_field* f);
+Sizes plan_sizes(const isr_field* f, int tile);
+int ctx_tile(const isr_ctx* c, int order, int precision);
 
 int enqueue_pipeline(isr_ctx* c, const Job& j, const Sizes& z, hipStream_t s, hipEvent_t* ev, bool fast);
 int run_compress(isr_ctx* c, const isr_field* f, isr_blob** out, isr_stats* st);

@@ -298,15 +298,27 @@ int tiles_per_comp(int order, long long n_elem) {
 }
 
 hipError_t launch_fast(int kind, int precision, const Job& j, int gx, hipStream_t s) {
+  if (j.tile > 0) {
+    if (precision == ISR_PREC_FP32) return launch_dense_fp32(kind, j, gx, s);
+    if (precision == ISR_PREC_BF16) return launch_dense_bf16(kind, j, gx, s);
+    return hipErrorInvalidValue;
+  }
   if (precision == ISR_PREC_FP64) return launch_fast_fp64(kind, j, gx, s);
   if (precision == ISR_PREC_FP32) return launch_fast_fp32(kind, j, gx, s);
   if (precision == ISR_PREC_BF16) return launch_fast_bf16(kind, j, gx, s);
   return hipErrorInvalidValue;
 }
 
-int resident_fast(int kind, int precision, int order) {
+int resident_fast(int kind, int precision, int order, int tile) {
   static int cache[3][3][16];
+  static int dcache[3][3][16][65];
   if (kind < 0 || kind > 2 || precision < 0 || precision > 2 || !fast_order(order, precision)) return 1;
+  if (tile > 0) {
+    if (precision == ISR_PREC_FP64 || tile > 64 || !dense_shape(order, tile)) return 1;
+    int& d = dcache[kind][precision][order][tile];
+    if (d == 0) d = precision == ISR_PREC_FP32 ? resident_dense_fp32(kind, order, tile) : resident_dense_bf16(kind, order, tile);
+    return d;
+  }
   int& c = cache[kind][precision][order];
   if (c == 0) {
     if (precision == ISR_PREC_FP64)

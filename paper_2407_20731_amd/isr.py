@@ -54,6 +54,10 @@ class isr_field(C.Structure):
                 ("reserved", C.c_int32), ("elem_jac", C.c_void_p), ("stream", C.c_void_p)]
 
 
+class isr_tune_report(C.Structure):
+    _fields_ = [("count", C.c_int32), ("tile", C.c_int32 * 16), ("ms", C.c_double * 16), ("best", C.c_int32)]
+
+
 class isr_stats(C.Structure):
     _fields_ = [("norm2", C.c_double * MAX_COMP), ("budget", C.c_double * MAX_COMP),
                 ("tau", C.c_double * MAX_COMP), ("dropped", C.c_double * MAX_COMP),
@@ -93,6 +97,9 @@ def load_library(path: str = LIB_PATH):
         "isr_blob_from_host": (I32, [P, P, U64, C.POINTER(P)]),
         "isr_blob_free": (None, [P]),
         "isr_gll_tables": (I32, [I32] + [P] * 7),
+        "isr_get_tile": (I32, [P, I32, I32, C.POINTER(I32)]),
+        "isr_set_tile": (I32, [P, I32, I32, I32]),
+        "isr_autotune": (I32, [P, C.POINTER(isr_field), I32, C.POINTER(isr_tune_report)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -238,9 +245,11 @@ def _stream_ptr(stream) -> int:
 
 
 class Context:
-    def __init__(self, device: int = 0, budget_bytes: int = 0, flags: int = 0, max_inflight: int = 0):
+    def __init__(self, device: int = 0, budget_bytes: int = 0, flags: int = 0, max_inflight: int = 0,
+                 autotune_path: Optional[str] = None):
         lib = load_library()
-        cfg = isr_config(device=device, flags=flags, hbm_budget_bytes=budget_bytes, max_inflight=max_inflight)
+        cfg = isr_config(device=device, flags=flags, hbm_budget_bytes=budget_bytes, max_inflight=max_inflight,
+                         autotune_path=autotune_path.encode() if autotune_path else None)
         h = C.c_void_p()
         self._blobs = weakref.WeakSet()
         self._h = C.c_void_p(0)
@@ -287,6 +296,25 @@ class Context:
         return isr_field(field=u.data_ptr(), n_elem=n_elem or E, order=order, ncomp=ncomp,
                          comp_stride=stride, tol=float(tol), precision=p, reserved=0,
                          elem_jac=jp, stream=_stream_ptr(stream))
+
+    def get_tile(self, order: int, precision) -> int:
+        """Tile shape in use for (order, precision): 0 = wave-tile engine, T = dense tiles of T elements."""
+        t = C.c_int32()
+        p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        _check(load_library().isr_get_tile(self._h, order, p, C.byref(t)), "isr_get_tile")
+        return t.value
+
+    def set_tile(self, order: int, precision, tile: int):
+        """Use tile shape `tile` (-1: built-in choice) for later requests of (order, precision)."""
+        p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        _check(load_library().isr_set_tile(self._h, order, p, int(tile)), "isr_set_tile")
+
+    def autotune(self, u, order: int, tol: float, precision, reps: int = 3) -> dict:
+        """Time every tile shape of (order, precision) on this field; keep the fastest."""
+        f = self._field(u, order, tol, precision)
+        r = isr_tune_report()
+        _check(load_library().isr_autotune(self._h, C.byref(f), int(reps), C.byref(r)), "isr_autotune")
+        return {"best": r.best, "ms": {int(r.tile[k]): float(r.ms[k]) for k in range(r.count)}}
 
     def compress(self, u, order: int, tol: float, precision="fp64", jac=None, stream=None) -> Blob:
         f = self._field(u, order, tol, precision, jac, stream)

@@ -52,8 +52,13 @@ def coef_bound(prec, order, u_elem_max):
                                          (10, 7, 1e-3), (11, 5, 1e-2), (9, 1, 1e-3)])
 def test_mixed_against_oracle(isr_ctx, prec, order, E, tol):
     print(f"[case] prec={prec} order={order} E={E} tol={tol}", flush=True)
+    check_mixed(isr_ctx, prec, order, E, tol, seed=200 + order)
+
+
+def check_mixed(isr_ctx, prec, order, E, tol, seed):
+    """Every property listed in the module docstring, for one request."""
     n = order + 1
-    u_np = synth.field(E, order, seed=200 + order)
+    u_np = synth.field(E, order, seed=seed)
     u = torch.from_numpy(u_np).cuda()
     blob = isr_ctx.compress(u, order, tol, prec)
     coef = isr_ctx.forward(u, order, prec).cpu().numpy().astype(np.float64)
