@@ -30,6 +30,11 @@
 #ifndef ISR_DENSE_MINB
 #define ISR_DENSE_MINB 3
 #endif
+// Blocks of one contraction kept in flight (independent LDS -> MFMA -> LDS chains).
+#ifndef ISR_DENSE_UNROLL
+#define ISR_DENSE_UNROLL 2
+#endif
+
 
 namespace isr {
 
@@ -48,6 +53,12 @@ struct EngD {
   static constexpr int LDSW = S * 64;          // floats of the wave buffer
   static constexpr int W = (n3 + 63) / 64;     // bitmap words per element
   static_assert(S <= 32, "dense slots per lane");
+  // window candidates staged per wave in pass A (n >= 9: half, so that the
+  // larger tables leave room for four workgroups per CU), and the workgroups
+  // per CU pass B is compiled for (n <= 7: four, 128 VGPRs, measured faster
+  // than three without spills)
+  static constexpr int CAPB = n >= 9 ? 128 : 256;
+  static constexpr int MINB_B = n <= 7 ? 4 : ISR_DENSE_MINB;  // (dense_minb_b below)
 
   struct Mats {
     float fa[4], fv[4];  // FP32 A-operand fragments (forward A, inverse V)
@@ -115,18 +126,34 @@ struct EngD {
     constexpr int ST = stride<AX>();
     const int P = lane & 15, g = lane >> 4;
     const int hc = g / GPC, a0 = 4 * (g % GPC);
-#pragma unroll 2
+#pragma unroll ISR_DENSE_UNROLL
     for (int b = 0; b < NB; ++b) {
       const int PI = PB * b + 16 * hc + P;
       const bool pv = PI < TP;
       float* p = buf + (pv ? pbase<AX>(PI) + a0 * ST : 0);
       float x[4], y[4];
+      if constexpr (AX == 0 && n % 2 == 0) {
+        // contiguous pairs of one pencil: 8-byte accesses (even n keeps them
+        // aligned and a pair either inside or outside the pencil)
+        typedef float fl2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-      for (int m = 0; m < 4; ++m) x[m] = (pv && a0 + m < n) ? p[m * ST] : 0.0f;
-      mfma(x, y, f, h, l);
+        for (int m = 0; m < 4; m += 2) {
+          const fl2 z = (pv && a0 + m < n) ? *(const fl2*)(p + m) : fl2{0.0f, 0.0f};
+          x[m] = z.x;
+          x[m + 1] = z.y;
+        }
+        mfma(x, y, f, h, l);
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
-        if (pv && a0 + m < n) p[m * ST] = y[m];
+        for (int m = 0; m < 4; m += 2)
+          if (pv && a0 + m < n) *(fl2*)(p + m) = fl2{y[m], y[m + 1]};
+      } else {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) x[m] = (pv && a0 + m < n) ? p[m * ST] : 0.0f;
+        mfma(x, y, f, h, l);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          if (pv && a0 + m < n) p[m * ST] = y[m];
+      }
     }
     asm volatile("" ::: "memory");
   }
@@ -144,11 +171,23 @@ struct EngD {
   }
 };
 
-// Element (within the tile) and flat index of dense position v.
+// pass B launch bound of order N (the kernel attribute takes no template-id)
+template <int N>
+constexpr int dense_minb_b() {
+  return N + 1 <= 7 ? 4 : ISR_DENSE_MINB;
+}
+
+// Element (within the tile) and flat index of dense position v (positions
+// past the tile, which are masked out, keep f inside the tables).
 template <class G>
 DEV void dense_ef(int v, int& e, int& f) {
-  e = v / G::n3;
-  f = v - e * G::n3;
+  if constexpr (G::TV == G::n3) {
+    e = 0;
+    f = v < G::n3 ? v : G::n3 - 1;
+  } else {
+    e = v / G::n3;
+    f = v - e * G::n3;
+  }
 }
 
 // ---- sample pass --------------------------------------------------------------
@@ -253,8 +292,8 @@ template <int N, int PREC, int T>
 struct PassALdsD {
   float buf[4][EngD<N, PREC, T>::LDSW];
   TabLdsL<EngD<N, PREC, T>::n3> tab;
-  u64 key[4][CAPB];
-  u32 idx[4][CAPB];
+  u64 key[4][EngD<N, PREC, T>::CAPB];
+  u32 idx[4][EngD<N, PREC, T>::CAPB];
   u32 ecnt[4][T];
   long long red[4][8];
 };
@@ -338,7 +377,7 @@ __global__ __launch_bounds__(256, ISR_DENSE_MINB) void k_passAD(Job j) {
           L.idx[wv][pos] = (u32)(e0 + e);
         }
         ncap += (u32)__popcll(bc);
-        if (ncap > (u32)(CAPB - 64)) {
+        if (ncap > (u32)(G::CAPB - 64)) {
           asm volatile("" ::: "memory");
           cap_flush(L.key[wv], L.idx[wv], ncap, st, list, lidx, j.list_cap, lane);
         }
@@ -388,7 +427,7 @@ struct PassBLdsD {
 };
 
 template <int N, int PREC, int T>
-__global__ __launch_bounds__(256, ISR_DENSE_MINB) void k_passBD(Job j) {
+__global__ __launch_bounds__(256, dense_minb_b<N>()) void k_passBD(Job j) {
   typedef EngD<N, PREC, T> G;
   constexpr int n3 = G::n3, S = G::S, W = G::W;
   __shared__ PassBLdsD<N, PREC, T> L;
