@@ -60,7 +60,8 @@ Arena::Arena(uint64_t budget) : budget_(budget) {}
 Arena::~Arena() { release(); }
 
 void Arena::release() {
-  for (auto& c : chunks_) (void)hipFree(c.base);
+  for (auto& c : chunks_)
+    if (c.base) (void)hipFree(c.base);
   chunks_.clear();
   live_.clear();
   held_ = 0;
@@ -83,8 +84,24 @@ void* Arena::alloc(size_t bytes, bool high) {
       }
   if (best_c < 0) {
     // a new chunk: 256 MB, or what is left of the budget, or at least `bytes`
-    size_t want = std::max(bytes, std::min((size_t)(256ull << 20), (size_t)(budget_ > held_ ? budget_ - held_ : 0)));
-    if (held_ + want > budget_) return nullptr;
+    auto wanted = [&] {
+      return std::max(bytes, std::min((size_t)(256ull << 20), (size_t)(budget_ > held_ ? budget_ - held_ : 0)));
+    };
+    size_t want = wanted();
+    if (held_ + want > budget_) {
+      // the budget is held in ranges too small for this request: give the
+      // chunks with nothing live in them back to the device and try again
+      for (auto& c : chunks_)
+        if (c.base && c.free.size() == 1 && c.free.begin()->first == 0 && c.free.begin()->second == c.size) {
+          (void)hipFree(c.base);
+          held_ -= c.size;
+          c.base = nullptr;
+          c.size = 0;
+          c.free.clear();
+        }
+      want = wanted();
+      if (held_ + want > budget_) return nullptr;
+    }
     void* p = nullptr;
     if (hipMalloc(&p, want) != hipSuccess) {
       (void)hipGetLastError();
@@ -94,9 +111,16 @@ void* Arena::alloc(size_t bytes, bool high) {
     c.base = (char*)p;
     c.size = want;
     c.free[0] = want;
-    chunks_.push_back(c);
+    best_c = -1;
+    for (size_t ci = 0; ci < chunks_.size() && best_c < 0; ++ci)
+      if (!chunks_[ci].base) best_c = (int)ci;  // reuse a released slot (live_ keeps indices)
+    if (best_c < 0) {
+      chunks_.push_back(c);
+      best_c = (int)chunks_.size() - 1;
+    } else {
+      chunks_[best_c] = c;
+    }
     held_ += want;
-    best_c = (int)chunks_.size() - 1;
     best_off = 0;
     best_sz = want;
   }

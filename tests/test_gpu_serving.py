@@ -89,3 +89,16 @@ def test_poll_unknown_and_pending():
             if b is not None:
                 break
         assert b is not None and b.status == isr.OK
+
+
+def test_arena_gives_back_empty_chunks():
+    """A request that needs most of the budget is admitted after smaller ones
+    have left the budget split into chunks with nothing live in them."""
+    from paper_2407_20731_amd import isr
+    small = synth.field_torch(1000, 7, ncomp=3, seed=51, device="cuda")
+    big = synth.field_torch(24000, 7, ncomp=3, seed=52, device="cuda")  # ~0.9 GB of scratch and blob
+    with isr.Context(device=0, budget_bytes=1 << 30) as ctx:
+        ctx.compress(small, 7, 1e-3, "bf16").free()
+        b = ctx.compress(big, 7, 1e-3, "bf16")
+        assert b.status == 0
+        b.free()
