@@ -124,8 +124,9 @@ def pools(orders, n_elem):
     return {N: synth.field_torch(n_elem, N, ncomp=NCOMP, seed=900 + N, device="cuda") for N in orders}
 
 
-def run_batch(ctx, pool, prec):
-    """Config 4: 32 snapshots, E log-uniform 4k-200k, N uniform in {5,7,9}."""
+def run_batch(ctx, pool, prec, reps=3):
+    """Config 4: 32 snapshots, E log-uniform 4k-200k, N uniform in {5,7,9}; the
+    median of `reps` timed batches after one untimed one."""
     import numpy as np
     import torch
 
@@ -137,18 +138,24 @@ def run_batch(ctx, pool, prec):
         off = int(rng.integers(0, pool[N].shape[1] - E + 1))
         fields.append((pool[N][:, off:off + E], N, TOL))
         nbytes += NCOMP * E * (N + 1) ** 3 * 8
-    ctx.compress_batch(fields[:4], prec)  # warm up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    blobs = ctx.compress_batch(fields, prec)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ok = all(b.status == 0 for b in blobs)
-    rel = max(max(b.stats["rel_err"]) for b in blobs)
-    for b in blobs:
+    # one untimed pass over the whole batch: the arena grows to its working
+    # set (device allocations) outside the timed region
+    for b in ctx.compress_batch(fields, prec):
         b.free()
-    return {"snapshots": 32, "total_GB": nbytes / 1e9, "seconds": dt, "GBps": nbytes / dt / 1e9,
-            "precision": prec, "all_ok": ok, "max_rel_err": rel}
+    times, ok, rel = [], True, 0.0
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        blobs = ctx.compress_batch(fields, prec)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        ok = ok and all(b.status == 0 for b in blobs)
+        rel = max(rel, max(max(b.stats["rel_err"]) for b in blobs))
+        for b in blobs:
+            b.free()
+    dt = sorted(times)[len(times) // 2]
+    return {"snapshots": 32, "total_GB": nbytes / 1e9, "seconds": dt, "GBps": nbytes / dt / 1e9, "reps": reps,
+            "seconds_each": times, "precision": prec, "all_ok": ok, "max_rel_err": rel}
 
 
 def run_serving(pool, prec, budget, n_req, rate_frac, tune_path=None):

@@ -762,7 +762,16 @@ int task_step(Task* t, isr_blob** out) {
 static int run_batch_concurrent(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_stats* st) {
   std::vector<uint64_t> ids(count, 0);
   std::vector<int> sub(count, ISR_OK);
-  for (int i = 0; i < count; ++i) sub[i] = c->sched->submit(&fs[i], &ids[i]);
+  // largest snapshots first: the last ones to start are short, so the
+  // streams drain together instead of one large pipeline running alone
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  auto work = [&](int i) {
+    const long long n = fs[i].order + 1;
+    return (long long)fs[i].n_elem * n * n * n * fs[i].ncomp;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+  for (int i : order) sub[i] = c->sched->submit(&fs[i], &ids[i]);
   int first = ISR_OK;
   for (int i = 0; i < count; ++i) {
     outs[i] = nullptr;
