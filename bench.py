@@ -63,6 +63,63 @@ def measured_traffic(prec: str):
 DTYPES = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
 
 
+def _counter_kib(csv_path: str, kernel: str, counter: str) -> float:
+    """Average per dispatch of one rocprofv3 counter (KiB) for kernels whose name starts with `kernel`."""
+    import csv
+    per = {}
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter and r["Kernel_Name"].startswith(kernel):
+                per[r["Dispatch_Id"]] = per.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    if not per:
+        raise SystemExit(f"no {counter} samples of {kernel} in {csv_path}")
+    return sum(per.values()) / len(per)
+
+
+def summarize_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib, commands) -> dict:
+    """HBM bytes of the compaction pass from two rocprofv3 --pmc runs, scaled by
+    what the same counters read for a plain device copy of copy_mib MiB."""
+    import hashlib
+    kern, copyk = "void isr::k_passB<7, 2>", "__amd_rocclr_copyBuffer"
+    moved = copy_mib * 1024.0  # KiB read, and KiB written, per copy
+    ff = moved / _counter_kib(copy_fetch_csv, copyk, "FETCH_SIZE")
+    fw = moved / _counter_kib(copy_write_csv, copyk, "WRITE_SIZE")
+    fetch = _counter_kib(fetch_csv, kern, "FETCH_SIZE")
+    write = _counter_kib(write_csv, kern, "WRITE_SIZE")
+    files = ["isr_common.cuh", "isr_engine.cuh", "isr_internal.h", "isr_passes.cuh", "isr_selbody.cuh", "isr_xsum.cuh"]
+    h = hashlib.sha256()
+    for name in files:
+        with open(os.path.join(ROOT, "paper_2407_20731_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return {"kernel": "k_passB<7, BF16>", "workload": "65,536 elements, N=7, 3 FP64 components, tol 1e-3",
+            "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write, "copy_factor_fetch": ff,
+            "copy_factor_write": fw, "traffic_bytes": (fetch * ff + write * fw) * 1024.0,
+            "source_files": files, "source_sha256": h.hexdigest(), "commands": commands}
+
+
+def summarize_trace(trace_csv: str, title: str, command: str) -> str:
+    """Markdown table of per-kernel durations from a rocprofv3 kernel trace."""
+    import csv
+    agg = {}
+    with open(trace_csv) as f:
+        for r in csv.DictReader(f):
+            if "isr::" not in r["Kernel_Name"]:
+                continue  # the library's kernels only (not torch's input generation)
+            d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            agg.setdefault(r["Kernel_Name"], []).append(d)
+    tot = sum(sum(v) for v in agg.values())
+    out = [f"# {title}", "", "Command (GPU box, repository root):", "", f"    {command}", "",
+           "Template arguments of the streaming kernels: order N, precision P (0 = FP64, 1 = FP32 MFMA, "
+           "2 = BF16-split MFMA), and for the dense-tile kernels (`...D`) the elements per wavefront tile.", "",
+           "| Kernel | Calls | Average (us) | Min (us) | Max (us) | Share |", "|---|---|---|---|---|---|"]
+    for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        if sum(v) / tot < 0.001:
+            continue
+        out.append(f"| `{k}` | {len(v)} | {sum(v) / len(v):.1f} | {min(v):.1f} | {max(v):.1f} | "
+                   f"{100 * sum(v) / tot:.1f} % |")
+    return "\n".join(out) + "\n"
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -229,7 +286,22 @@ def main() -> int:
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in tile shapes (no autotuning)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_CSV", "TITLE", "COMMAND"),
+                    help="print a markdown kernel-time table from a rocprofv3 kernel trace (no GPU)")
+    ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="write the compaction pass's HBM traffic file from four rocprofv3 --pmc runs (no GPU)")
+    ap.add_argument("--traffic-commands", nargs="*", default=[], help="the commands of those four runs")
     args = ap.parse_args()
+    if args.summarize_trace:
+        print(summarize_trace(*args.summarize_trace), end="")
+        return 0
+    if args.summarize_traffic:
+        rec = summarize_traffic(*args.summarize_traffic, 1024, args.traffic_commands)
+        with open(TRAFFIC_FILE, "w") as f:
+            json.dump(rec, f, indent=1)
+            f.write("\n")
+        print(json.dumps(rec))
+        return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path is single-GPU "
               "by design; see the sharding notes in DESIGN.md)", file=sys.stderr)
