@@ -66,6 +66,9 @@ extern "C" {
 
 /* ---- context flags ---------------------------------------------------- */
 #define ISR_FLAG_TIMING 1u  /* record device time per phase into isr_stats */
+#define ISR_FLAG_BATCH_PERSISTENT 2u /* FP32/BF16 batches of orders 5/7/9: one persistent launch of
+                                        the streaming path; default: one streaming pipeline per
+                                        snapshot on the scheduler's streams (faster today) */
 
 #define ISR_MAX_COMP 8
 #define ISR_MAX_ORDER 15
@@ -139,10 +142,12 @@ typedef struct {
   int32_t repair_iters;
   int32_t status;
   int32_t precision;
-  int32_t path;                  /* 1: streaming path (orders 1..7, threshold
-                                    inside the sampled window); 0: general
-                                    pipeline (other orders, or the window
-                                    missed and the request was rerun) */
+  int32_t path;                  /* 1: streaming path (threshold inside the
+                                    sampled window); 2: the same, inside the
+                                    persistent batch launch; 0: general
+                                    pipeline (orders without a streaming path,
+                                    or the window missed and the request was
+                                    rerun) */
 } isr_stats;
 
 /* Create a context on cfg->device (cfg may be NULL: device 0, defaults).

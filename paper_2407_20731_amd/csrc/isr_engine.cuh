@@ -341,7 +341,7 @@ struct SampleLds {
   typename Eng<N, PREC>::wt buf[4][Eng<N, PREC>::LDSW];
   TabLds tab;
   u32 hc[SBINS];
-  double hs[SBINS];
+  float hs[SBINS];  // sums of energy / 2^(bin exponent), each term in [1, 2)
   double u2[4];
   int maxe;
   int last;
@@ -422,16 +422,14 @@ DEV void select_sample_body(const Job& j, int comp) {
 }
 
 template <int N, int PREC>
-__global__ __launch_bounds__(256, ISR_FAST_MINB) void k_sample(Job j) {
+DEV void sample_body(const Job& j, int comp, int vb, int nvb, SampleLds<N, PREC>& L) {
   typedef Eng<N, PREC> G;
   constexpr int n3 = G::n3, NS = G::NS, EPW = G::EPW;
-  __shared__ SampleLds<N, PREC> L;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int comp = blockIdx.y;
   CompState* st = j.st + comp;
   for (int k = tid; k < SBINS; k += 256) {
     L.hc[k] = 0u;
-    L.hs[k] = 0.0;
+    L.hs[k] = 0.0f;
   }
   if (tid == 0) L.maxe = 0;
   typename G::Mats mt;
@@ -444,10 +442,10 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_sample(Job j) {
   const long long stiles = (tiles + ss - 1) / ss;
   const double* ub = j.u + (size_t)comp * j.comp_stride;
   const bool vec = ((((uintptr_t)ub) & 15) == 0);
-  const long long nw = (long long)gridDim.x * 4;
+  const long long nw = (long long)nvb * 4;
   double u2 = 0.0;
   int maxe = 0;
-  for (long long k = (long long)blockIdx.x * 4 + wv; k < stiles; k += nw) {
+  for (long long k = (long long)vb * 4 + wv; k < stiles; k += nw) {
     const long long t = k * ss;
     const long long e0 = t * EPW;
     const int ne = (int)((E - e0) < EPW ? (E - e0) : EPW);
@@ -469,7 +467,7 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_sample(Job j) {
       const int b = bits_exp(dbits(en));
       if (v && b < HBINS - 1) {  // rounded sums only place the window
         atomicAdd(&L.hc[b], 1u);
-        atomicAdd(&L.hs[b], en);
+        atomicAdd(&L.hs[b], (float)ldexp(en, 1023 - b));
       }
     }
   }
@@ -487,15 +485,21 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_sample(Job j) {
   for (int k = tid; k < SBINS; k += 256) {
     if (L.hc[k]) {
       atomicAdd(&H[k].cnt, (u64)L.hc[k]);
-      atomicAdd((double*)&H[k].lo, L.hs[k]);
+      atomicAdd((double*)&H[k].lo, ldexp((double)L.hs[k], k - 1023));
     }
   }
   if (tid == 0) {
     atomicAdd(&st->samp_u2, L.u2[0] + L.u2[1] + L.u2[2] + L.u2[3]);
     atomicMax(&st->samp_maxe, L.maxe);
   }
-  if (!last_block(j.done + D_SAMPLE * 8 + comp, &L.last, gridDim.x)) return;
+  if (!last_block(j.done + D_SAMPLE * 8 + comp, &L.last, nvb)) return;
   if (tid < 64) select_sample_body(j, comp);
+}
+
+template <int N, int PREC>
+__global__ __launch_bounds__(256, ISR_FAST_MINB) void k_sample(Job j) {
+  __shared__ SampleLds<N, PREC> L;
+  sample_body<N, PREC>(j, blockIdx.y, blockIdx.x, gridDim.x, L);
 }
 
 // ---- pass A -------------------------------------------------------------------
@@ -530,13 +534,11 @@ DEV void cap_flush(u64* key, u32* idx, u32& ncap, CompState* st, u64* list, u32*
 }
 
 template <int N, int PREC>
-__global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passA(Job j) {
+DEV void passA_body(const Job& j, int comp, int vb, int nvb, PassALds<N, PREC>& L) {
   typedef Eng<N, PREC> G;
   constexpr int n3 = G::n3, NS = G::NS, EPW = G::EPW;
   constexpr bool EXACT = PREC == P_FP64;
-  __shared__ PassALds<N, PREC> L;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int comp = blockIdx.y;
   CompState* st = j.st + comp;
   if (st->flags & ST_MISS) return;
   const int wlo = st->win_lo, whi = st->win_hi;
@@ -558,14 +560,14 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passA(Job j) {
   u32 ncap = 0u;
   const double* ub = j.u + (size_t)comp * j.comp_stride;
   const bool vec = ((((uintptr_t)ub) & 15) == 0);
-  const long long nw = (long long)gridDim.x * 4;
+  const long long nw = (long long)nvb * 4;
   // the next tile's field values are loaded while this one is processed
   double un[NS];
   {
-    const long long t0 = (long long)blockIdx.x * 4 + wv;
+    const long long t0 = (long long)vb * 4 + wv;
     if (t0 < tiles) G::load(ub + t0 * EPW * n3, (int)((E - t0 * EPW) < EPW ? (E - t0 * EPW) : EPW), vec, un, lane);
   }
-  for (long long t = (long long)blockIdx.x * 4 + wv; t < tiles; t += nw) {
+  for (long long t = (long long)vb * 4 + wv; t < tiles; t += nw) {
     const long long e0 = t * EPW;
     const int ne = (int)((E - e0) < EPW ? (E - e0) : EPW);
     double u[NS], c[NS];
@@ -650,7 +652,13 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passA(Job j) {
   v[5] = ke[2];
   v[6] = lane == 0 ? (long long)hi_tot : 0ll;
   block_sum_i64<7>(v, L.red, tid);
-  if (tid < 7) j.slotsA[((size_t)comp * j.gA + blockIdx.x) * 8 + tid] = L.red[0][tid];
+  if (tid < 7) j.slotsA[((size_t)comp * j.gA + vb) * 8 + tid] = L.red[0][tid];
+}
+
+template <int N, int PREC>
+__global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passA(Job j) {
+  __shared__ PassALds<N, PREC> L;
+  passA_body<N, PREC>(j, blockIdx.y, blockIdx.x, gridDim.x, L);
 }
 
 // ---- pass B -------------------------------------------------------------------
@@ -666,14 +674,12 @@ struct PassBLds {
 };
 
 template <int N, int PREC>
-__global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passB(Job j) {
+DEV void passB_body(const Job& j, int comp, int vb, int nvb, PassBLds<N, PREC>& L) {
   typedef Eng<N, PREC> G;
   constexpr int n3 = G::n3, NS = G::NS, EPW = G::EPW, W = G::W;
   constexpr bool EXACT = PREC == P_FP64;
   static_assert(EPW * W <= 16, "tile bitmap fits the LDS slot");
-  __shared__ PassBLds<N, PREC> L;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int comp = blockIdx.y;
   CompState* st = j.st + comp;
   if (st->flags & ST_MISS) return;
   const XParm PR = xparm(st->xm_err, j.xh);
@@ -694,16 +700,16 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passB(Job j) {
   bool bad = false;
   const double* ub = j.u + (size_t)comp * j.comp_stride;
   const bool vec = ((((uintptr_t)ub) & 15) == 0);
-  const long long nw = (long long)gridDim.x * 4;
+  const long long nw = (long long)nvb * 4;
   u64* bm = L.bm[wv];
   u32* wp = L.wp[wv];
   // the next tile's field values are loaded while this one is processed
   double un[NS];
   {
-    const long long t0 = (long long)blockIdx.x * 4 + wv;
+    const long long t0 = (long long)vb * 4 + wv;
     if (t0 < tiles) G::load(ub + t0 * EPW * n3, (int)((E - t0 * EPW) < EPW ? (E - t0 * EPW) : EPW), vec, un, lane);
   }
-  for (long long t = (long long)blockIdx.x * 4 + wv; t < tiles; t += nw) {
+  for (long long t = (long long)vb * 4 + wv; t < tiles; t += nw) {
     const long long e0 = t * EPW;
     const int ne = (int)((E - e0) < EPW ? (E - e0) : EPW);
     double u[NS], c[NS];
@@ -851,8 +857,8 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passB(Job j) {
   long long v[3];
   xints(ar, PR, v);
   block_sum_i64<3>(v, L.red, tid);
-  if (tid < 3) j.slotsB[((size_t)comp * j.gB + blockIdx.x) * 4 + tid] = L.red[0][tid];
-  if (!last_block(j.done + D_PASSB * 8 + comp, &L.last, gridDim.x)) return;
+  if (tid < 3) j.slotsB[((size_t)comp * j.gB + vb) * 4 + tid] = L.red[0][tid];
+  if (!last_block(j.done + D_PASSB * 8 + comp, &L.last, nvb)) return;
   // the component's error total, then its final statistics
   __int128 K[3];
   for (int k = 0; k < 3; ++k) K[k] = block_total_rows(j.slotsB + (size_t)comp * j.gB * 4, j.gB, 4, k, L.part, tid);
@@ -860,6 +866,12 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passB(Job j) {
   __threadfence();
   __syncthreads();
   if (tid < 64) finalize_body(j, comp);
+}
+
+template <int N, int PREC>
+__global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passB(Job j) {
+  __shared__ PassBLds<N, PREC> L;
+  passB_body<N, PREC>(j, blockIdx.y, blockIdx.x, gridDim.x, L);
 }
 
 // ---- launchers ------------------------------------------------------------------

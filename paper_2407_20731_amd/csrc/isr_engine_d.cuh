@@ -196,23 +196,21 @@ struct SampleLdsD {
   float buf[4][EngD<N, PREC, T>::LDSW];
   TabLdsL<EngD<N, PREC, T>::n3> tab;
   u32 hc[SBINS];
-  double hs[SBINS];
+  float hs[SBINS];  // sums of energy / 2^(bin exponent), each term in [1, 2)
   double u2[4];
   int maxe;
   int last;
 };
 
 template <int N, int PREC, int T>
-__global__ __launch_bounds__(256, ISR_DENSE_MINB) void k_sampleD(Job j) {
+DEV void sampleD_body(const Job& j, int comp, int vb, int nvb, SampleLdsD<N, PREC, T>& L) {
   typedef EngD<N, PREC, T> G;
   constexpr int n3 = G::n3, S = G::S;
-  __shared__ SampleLdsD<N, PREC, T> L;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int comp = blockIdx.y;
   CompState* st = j.st + comp;
   for (int k = tid; k < SBINS; k += 256) {
     L.hc[k] = 0u;
-    L.hs[k] = 0.0;
+    L.hs[k] = 0.0f;
   }
   if (tid == 0) L.maxe = 0;
   typename G::Mats mt;
@@ -223,11 +221,11 @@ __global__ __launch_bounds__(256, ISR_DENSE_MINB) void k_sampleD(Job j) {
   const long long ss = j.sample_stride > 0 ? j.sample_stride : 1;
   const long long stiles = (tiles + ss - 1) / ss;
   const double* ub = j.u + (size_t)comp * j.comp_stride;
-  const long long nw = (long long)gridDim.x * 4;
+  const long long nw = (long long)nvb * 4;
   float* buf = L.buf[wv];
   double u2 = 0.0;
   int maxe = 0;
-  for (long long k = (long long)blockIdx.x * 4 + wv; k < stiles; k += nw) {
+  for (long long k = (long long)vb * 4 + wv; k < stiles; k += nw) {
     const long long e0 = k * ss * T;
     const int nv = (int)((E - e0) < T ? (E - e0) : T) * n3;
     const double* tile = ub + e0 * n3;
@@ -257,7 +255,7 @@ __global__ __launch_bounds__(256, ISR_DENSE_MINB) void k_sampleD(Job j) {
       const int b = bits_exp(dbits(en));
       if (b < HBINS - 1) {  // rounded sums only place the window
         atomicAdd(&L.hc[b], 1u);
-        atomicAdd(&L.hs[b], en);
+        atomicAdd(&L.hs[b], (float)ldexp(en, 1023 - b));
       }
     }
     asm volatile("" ::: "memory");
@@ -276,15 +274,21 @@ __global__ __launch_bounds__(256, ISR_DENSE_MINB) void k_sampleD(Job j) {
   for (int k = tid; k < SBINS; k += 256) {
     if (L.hc[k]) {
       atomicAdd(&H[k].cnt, (u64)L.hc[k]);
-      atomicAdd((double*)&H[k].lo, L.hs[k]);
+      atomicAdd((double*)&H[k].lo, ldexp((double)L.hs[k], k - 1023));
     }
   }
   if (tid == 0) {
     atomicAdd(&st->samp_u2, L.u2[0] + L.u2[1] + L.u2[2] + L.u2[3]);
     atomicMax(&st->samp_maxe, L.maxe);
   }
-  if (!last_block(j.done + D_SAMPLE * 8 + comp, &L.last, gridDim.x)) return;
+  if (!last_block(j.done + D_SAMPLE * 8 + comp, &L.last, nvb)) return;
   if (tid < 64) select_sample_body(j, comp);
+}
+
+template <int N, int PREC, int T>
+__global__ __launch_bounds__(256, ISR_DENSE_MINB) void k_sampleD(Job j) {
+  __shared__ SampleLdsD<N, PREC, T> L;
+  sampleD_body<N, PREC, T>(j, blockIdx.y, blockIdx.x, gridDim.x, L);
 }
 
 // ---- pass A ---------------------------------------------------------------------
@@ -299,12 +303,10 @@ struct PassALdsD {
 };
 
 template <int N, int PREC, int T>
-__global__ __launch_bounds__(256, ISR_DENSE_MINB) void k_passAD(Job j) {
+DEV void passAD_body(const Job& j, int comp, int vb, int nvb, PassALdsD<N, PREC, T>& L) {
   typedef EngD<N, PREC, T> G;
   constexpr int n3 = G::n3, S = G::S;
-  __shared__ PassALdsD<N, PREC, T> L;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int comp = blockIdx.y;
   CompState* st = j.st + comp;
   if (st->flags & ST_MISS) return;
   const int wlo = st->win_lo, whi = st->win_hi;
@@ -325,9 +327,9 @@ __global__ __launch_bounds__(256, ISR_DENSE_MINB) void k_passAD(Job j) {
   u64 hi_tot = 0ull;
   u32 ncap = 0u;
   const double* ub = j.u + (size_t)comp * j.comp_stride;
-  const long long nw = (long long)gridDim.x * 4;
+  const long long nw = (long long)nvb * 4;
   float* buf = L.buf[wv];
-  for (long long t = (long long)blockIdx.x * 4 + wv; t < tiles; t += nw) {
+  for (long long t = (long long)vb * 4 + wv; t < tiles; t += nw) {
     const long long e0 = t * T;
     const int ne = (int)((E - e0) < T ? (E - e0) : T), nv = ne * n3;
     const double* tile = ub + e0 * n3;
@@ -411,7 +413,13 @@ __global__ __launch_bounds__(256, ISR_DENSE_MINB) void k_passAD(Job j) {
   v[5] = ke[2];
   v[6] = lane == 0 ? (long long)hi_tot : 0ll;
   block_sum_i64<7>(v, L.red, tid);
-  if (tid < 7) j.slotsA[((size_t)comp * j.gA + blockIdx.x) * 8 + tid] = L.red[0][tid];
+  if (tid < 7) j.slotsA[((size_t)comp * j.gA + vb) * 8 + tid] = L.red[0][tid];
+}
+
+template <int N, int PREC, int T>
+__global__ __launch_bounds__(256, ISR_DENSE_MINB) void k_passAD(Job j) {
+  __shared__ PassALdsD<N, PREC, T> L;
+  passAD_body<N, PREC, T>(j, blockIdx.y, blockIdx.x, gridDim.x, L);
 }
 
 // ---- pass B ---------------------------------------------------------------------
@@ -427,12 +435,10 @@ struct PassBLdsD {
 };
 
 template <int N, int PREC, int T>
-__global__ __launch_bounds__(256, dense_minb_b<N>()) void k_passBD(Job j) {
+DEV void passBD_body(const Job& j, int comp, int vb, int nvb, PassBLdsD<N, PREC, T>& L) {
   typedef EngD<N, PREC, T> G;
   constexpr int n3 = G::n3, S = G::S, W = G::W;
-  __shared__ PassBLdsD<N, PREC, T> L;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int comp = blockIdx.y;
   CompState* st = j.st + comp;
   if (st->flags & ST_MISS) return;
   const XParm PR = xparm(st->xm_err, j.xh);
@@ -452,11 +458,11 @@ __global__ __launch_bounds__(256, dense_minb_b<N>()) void k_passBD(Job j) {
   double pr = 0.0;  // fixed-order sum of the error terms
   bool bad = false;
   const double* ub = j.u + (size_t)comp * j.comp_stride;
-  const long long nw = (long long)gridDim.x * 4;
+  const long long nw = (long long)nvb * 4;
   float* buf = L.buf[wv];
   u64* bal = L.bal[wv];
   const u64 lt = (1ull << lane) - 1ull;
-  for (long long t = (long long)blockIdx.x * 4 + wv; t < tiles; t += nw) {
+  for (long long t = (long long)vb * 4 + wv; t < tiles; t += nw) {
     const long long e0 = t * T;
     const int ne = (int)((E - e0) < T ? (E - e0) : T), nv = ne * n3;
     const double* tile = ub + e0 * n3;
@@ -550,14 +556,20 @@ __global__ __launch_bounds__(256, dense_minb_b<N>()) void k_passBD(Job j) {
   long long v[3];
   xints(ar, PR, v);
   block_sum_i64<3>(v, L.red, tid);
-  if (tid < 3) j.slotsB[((size_t)comp * j.gB + blockIdx.x) * 4 + tid] = L.red[0][tid];
-  if (!last_block(j.done + D_PASSB * 8 + comp, &L.last, gridDim.x)) return;
+  if (tid < 3) j.slotsB[((size_t)comp * j.gB + vb) * 4 + tid] = L.red[0][tid];
+  if (!last_block(j.done + D_PASSB * 8 + comp, &L.last, nvb)) return;
   __int128 K[3];
   for (int k = 0; k < 3; ++k) K[k] = block_total_rows(j.slotsB + (size_t)comp * j.gB * 4, j.gB, 4, k, L.part, tid);
   if (tid == 0) emit_total(gR, K, PR.m, PR.h, -1);
   __threadfence();
   __syncthreads();
   if (tid < 64) finalize_body(j, comp);
+}
+
+template <int N, int PREC, int T>
+__global__ __launch_bounds__(256, dense_minb_b<N>()) void k_passBD(Job j) {
+  __shared__ PassBLdsD<N, PREC, T> L;
+  passBD_body<N, PREC, T>(j, blockIdx.y, blockIdx.x, gridDim.x, L);
 }
 
 // ---- launchers ------------------------------------------------------------------

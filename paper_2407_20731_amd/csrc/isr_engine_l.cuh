@@ -142,7 +142,7 @@ struct SampleLdsL {
   float buf[4][EngL<N, PREC>::LDSW];
   TabLdsL<EngL<N, PREC>::n3> tab;
   u32 hc[SBINS];
-  double hs[SBINS];
+  float hs[SBINS];  // sums of energy / 2^(bin exponent), each term in [1, 2)
   double u2[4];
   int maxe;
   int last;
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256, 2) void k_sampleL(Job j) {
   CompState* st = j.st + comp;
   for (int k = tid; k < SBINS; k += 256) {
     L.hc[k] = 0u;
-    L.hs[k] = 0.0;
+    L.hs[k] = 0.0f;
   }
   if (tid == 0) L.maxe = 0;
   typename G::Mats mt;
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(256, 2) void k_sampleL(Job j) {
         const int bb = bits_exp(dbits(en));
         if (bb < HBINS - 1) {
           atomicAdd(&L.hc[bb], 1u);
-          atomicAdd(&L.hs[bb], en);
+          atomicAdd(&L.hs[bb], (float)ldexp(en, 1023 - bb));
         }
       }
     }
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(256, 2) void k_sampleL(Job j) {
   for (int k = tid; k < SBINS; k += 256) {
     if (L.hc[k]) {
       atomicAdd(&H[k].cnt, (u64)L.hc[k]);
-      atomicAdd((double*)&H[k].lo, L.hs[k]);
+      atomicAdd((double*)&H[k].lo, ldexp((double)L.hs[k], k - 1023));
     }
   }
   if (tid == 0) {

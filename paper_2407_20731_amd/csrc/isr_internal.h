@@ -253,6 +253,29 @@ int resident_fast_fp32(int kind, int order);
 int resident_fast_bf16(int kind, int order);
 hipError_t launch_gather(const Job& j, int grid_x, hipStream_t s);
 hipError_t launch_count(const Job& j, int grid_x, hipStream_t s);
+constexpr int SCAN_CHUNK = 1024;  // elements per chunk of the element-offset scan
+inline int scan_grid_elems(long long n_elem) {  // its workgroups per component
+  const long long nch = (n_elem + SCAN_CHUNK - 1) / SCAN_CHUNK;
+  return (int)(nch < 1024 ? nch : 1024);
+}
+
+// Persistent batch launch of the streaming path (isr_fbatch.cuh, FP32 and
+// BF16): its phases, in queue order, and the tile shape it holds per order
+// (orders 5, 7, 9; -1: not in the persistent kernel).
+enum FastBatchPhase {
+  FQ_SAMPLE = 0, FQ_PASSA, FQ_GATHER, FQ_R2, FQ_R3, FQ_R4, FQ_R5, FQ_R6, FQ_COUNT, FQ_SCAN1, FQ_SCAN2, FQ_PASSB, NFQ
+};
+static_assert(NFQ <= NPH, "phase offsets of BatchCtl");
+inline int fbatch_tile(int order) { return order == 5 ? 4 : order == 7 ? 0 : order == 9 ? 1 : -1; }
+hipError_t launch_fbatch(int precision, const BatchCtl& B, int grid, size_t lds_bytes, hipStream_t s);
+size_t fbatch_lds(int precision);
+int fbatch_resident(int precision, size_t lds_bytes);
+hipError_t launch_fbatch_fp32(const BatchCtl& B, int grid, size_t lds, hipStream_t s);
+hipError_t launch_fbatch_bf16(const BatchCtl& B, int grid, size_t lds, hipStream_t s);
+size_t fbatch_lds_fp32();
+size_t fbatch_lds_bf16();
+int fbatch_resident_fp32(size_t lds);
+int fbatch_resident_bf16(size_t lds);
 
 // Host tables (isr_tables.cpp): correctly rounded FP64 values.
 struct HostTables {

@@ -401,8 +401,15 @@ namespace isr {
 // the finalize step.  A threshold outside the sampled window sets ST_MISS in
 // the selection; every later kernel then returns at once and the host runs
 // the general pipeline.
-static int enqueue_fast(isr_ctx* c, const Job& j0, const Sizes& z, hipStream_t s, hipEvent_t* ev) {
-  Job j = j0;
+// Grids of the streaming path's phases for job j (workgroups per component),
+// and the passes' grids and extraction headroom stored in j.  The persistent
+// batch launch uses the same values, so a snapshot's results do not depend on
+// how it was launched.
+struct FastGrids {
+  int gs, gl, rgx, gsc;  // sample, list passes (gather, count), refinement levels, offset scans
+};
+
+static FastGrids fast_setup(isr_ctx* c, Job& j, const Sizes& z) {
   const int nc = j.ncomp, prec = j.precision;
   const long long epw = fast_epw(j.order, j.tile);
   const long long ftiles = (j.n_elem + epw - 1) / epw;
@@ -420,26 +427,39 @@ static int enqueue_fast(isr_ctx* c, const Job& j0, const Sizes& z, hipStream_t s
   int h = 1;
   while ((1ll << (h - 1)) < terms) ++h;
   j.xh = std::max(7, std::min(20, h));
+  FastGrids g;
+  const long long ss = j.sample_stride > 0 ? j.sample_stride : 1;
+  const long long stiles = (ftiles + ss - 1) / ss;
+  g.gs = (int)std::max<long long>(1, std::min<long long>(64, (stiles + 15) / 16));
+  // list passes over ~2 % of the values; few refinement workgroups (each
+  // flushes up to RBINS sub-bins with global atomics)
+  g.gl = (int)std::max<long long>(1, std::min<long long>(GATHER_GMAX, (long long)(z.nv >> 17) + 1));
+  g.rgx = std::max(1, std::min(64, (int)(z.nv >> 20) + 1));
+  g.gsc = scan_grid_elems(j.n_elem);
+  return g;
+}
+
+// Streaming path: sample, pass A, exact window bins and level-1 selection,
+// refinement, per-element counts and offsets, pass B with the finalize step.
+// A threshold outside the sampled window sets ST_MISS in the selection; every
+// later kernel then returns at once and the host runs the general pipeline.
+static int enqueue_fast(isr_ctx* c, const Job& j0, const Sizes& z, hipStream_t s, hipEvent_t* ev) {
+  Job j = j0;
+  const int prec = j.precision;
+  const FastGrids g = fast_setup(c, j, z);
   auto rec = [&](int k) {
     if (ev) (void)hipEventRecord(ev[k], s);
   };
   HIPCHK(launch_zero((void*)j.histE, z.zero_bytes, s));
   rec(0);
-  const long long ss = j.sample_stride > 0 ? j.sample_stride : 1;
-  const long long stiles = (ftiles + ss - 1) / ss;
-  const int gs = (int)std::max<long long>(1, std::min<long long>(64, (stiles + 15) / 16));
-  HIPCHK(launch_fast(F_SAMPLE, prec, j, gs, s));
+  HIPCHK(launch_fast(F_SAMPLE, prec, j, g.gs, s));
   HIPCHK(launch_fast(F_PASSA, prec, j, j.gA, s));
   rec(1);
-  // list passes over ~2 % of the values
-  const int gl = (int)std::max<long long>(1, std::min<long long>(GATHER_GMAX, (long long)(z.nv >> 17) + 1));
-  HIPCHK(launch_gather(j, gl, s));
+  HIPCHK(launch_gather(j, g.gl, s));
   rec(2);
   rec(3);
-  // few workgroups: each flushes up to RBINS sub-bins with global atomics
-  const int rgx = std::max(1, std::min(64, (int)(z.nv >> 20) + 1));
-  for (int L = 2; L <= NLEV; ++L) HIPCHK(launch_refsel(j, L, rgx, s));
-  HIPCHK(launch_count(j, gl, s));
+  for (int L = 2; L <= NLEV; ++L) HIPCHK(launch_refsel(j, L, g.rgx, s));
+  HIPCHK(launch_count(j, g.gl, s));
   rec(4);
   HIPCHK(launch_fast(F_PASSB, prec, j, j.gB, s));
   rec(5);
@@ -783,17 +803,211 @@ static int run_batch_concurrent(isr_ctx* c, const isr_field* fs, int count, isr_
   return first;
 }
 
+// FP32 / BF16 batch of orders 5, 7, 9 (each with the tile shape the
+// persistent kernel holds): one persistent launch of the streaming path
+// (isr_fbatch.cuh).  A snapshot whose threshold fell outside its sampled
+// window, or whose error needs a rounding repair, is then compressed alone,
+// which is what it would have got alone as well.
+static int run_batch_stream(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_stats* st) {
+  const int prec = fs[0].precision;
+  hipStream_t s = (hipStream_t)fs[0].stream;
+  const double t_start = now_s();
+  struct Snap {
+    Sizes z;
+    char* scratch = nullptr;
+    isr_blob* b = nullptr;
+    Job j;
+    FastGrids g;
+    CompState* hs = nullptr;
+  };
+  std::vector<Snap> sn(count);
+  auto cleanup = [&]() {
+    for (auto& x : sn) {
+      if (x.scratch) c->arena->free(x.scratch);
+      if (x.b) {
+        c->arena->free(x.b->dev);
+        delete x.b;
+      }
+      put_host_state(c, x.hs);
+      x = Snap();
+    }
+  };
+  for (int i = 0; i < count; ++i) {
+    outs[i] = nullptr;
+    Snap& x = sn[i];
+    x.z = plan_sizes(&fs[i], fbatch_tile(fs[i].order));
+    x.scratch = (char*)c->arena->alloc(x.z.scratch_bytes);
+    x.b = x.scratch ? new_blob(c, &fs[i], x.z) : nullptr;
+    x.hs = grab_host_state(c);
+    if (!x.scratch || !x.b || !x.hs) {
+      cleanup();
+      return fail(ISR_ENOMEM, "batch of %d snapshots does not fit the HBM budget", count);
+    }
+    x.j = make_job(c, &fs[i], x.z, x.scratch, x.b);
+    x.g = fast_setup(c, x.j, x.z);
+  }
+  // pairs of the largest snapshots first in every phase: their passes start
+  // first, so their selection chains are ready when the queue reaches them and
+  // few workgroups spin on unfinished dependencies
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sn[a].z.nv > sn[b].z.nv; });
+  std::vector<int> psnap, pcomp;
+  for (int i : order)
+    for (int cc = 0; cc < fs[i].ncomp; ++cc) {
+      psnap.push_back(i);
+      pcomp.push_back(cc);
+    }
+  const int np = (int)psnap.size();
+  std::vector<long long> items((size_t)NFQ * (np + 1), 0);
+  BatchCtl B;
+  std::memset(&B, 0, sizeof(B));
+  B.npairs = np;
+  long long off = 0;
+  for (int ph = 0; ph < NFQ; ++ph) {
+    B.phase_off[ph] = off;
+    long long* row = &items[(size_t)ph * (np + 1)];
+    row[0] = 0;
+    for (int q = 0; q < np; ++q) {
+      const Snap& x = sn[psnap[q]];
+      long long cnt = 1;
+      if (ph == FQ_SAMPLE)
+        cnt = x.g.gs;
+      else if (ph == FQ_PASSA)
+        cnt = x.j.gA;
+      else if (ph == FQ_PASSB)
+        cnt = x.j.gB;
+      else if (ph == FQ_GATHER || ph == FQ_COUNT)
+        cnt = x.g.gl;
+      else if (ph == FQ_SCAN1 || ph == FQ_SCAN2)
+        cnt = x.g.gsc;
+      else
+        cnt = x.g.rgx;
+      row[q + 1] = row[q] + cnt;
+    }
+    off += row[np];
+  }
+  B.phase_off[NFQ] = off;
+  const size_t sz_jobs = sizeof(Job) * count, sz_pairs = sizeof(int) * np, sz_items = sizeof(long long) * items.size(),
+               sz_done = sizeof(u32) * NFQ * np;
+  auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+  const size_t o_jobs = 0, o_ps = al(sz_jobs), o_pc = o_ps + al(sz_pairs), o_items = o_pc + al(sz_pairs),
+               o_done = o_items + al(sz_items), o_ticket = o_done + al(sz_done), o_err = o_ticket + 256,
+               total = o_err + 256;
+  char* tab = (char*)c->arena->alloc(total);
+  if (!tab) {
+    cleanup();
+    return fail(ISR_ENOMEM, "batch tables do not fit the HBM budget");
+  }
+  std::vector<char> host(total, 0);
+  for (int i = 0; i < count; ++i) std::memcpy(host.data() + o_jobs + sizeof(Job) * i, &sn[i].j, sizeof(Job));
+  std::memcpy(host.data() + o_ps, psnap.data(), sz_pairs);
+  std::memcpy(host.data() + o_pc, pcomp.data(), sz_pairs);
+  std::memcpy(host.data() + o_items, items.data(), sz_items);
+  B.jobs = (const Job*)(tab + o_jobs);
+  B.pair_snap = (const int*)(tab + o_ps);
+  B.pair_comp = (const int*)(tab + o_pc);
+  B.items = (const long long*)(tab + o_items);
+  B.done = (u32*)(tab + o_done);
+  B.ticket = (unsigned long long*)(tab + o_ticket);
+  B.err = (int*)(tab + o_err);
+  int rc = ISR_OK;
+  int err_host = 0;
+  do {
+    for (int i = 1; i < count; ++i) {
+      if (fs[i].stream == fs[0].stream) continue;
+      hipEvent_t e;
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess) {
+        (void)hipEventRecord(e, (hipStream_t)fs[i].stream);
+        (void)hipStreamWaitEvent(s, e, 0);
+        (void)hipEventDestroy(e);
+      }
+    }
+    if (hipMemcpyAsync(tab, host.data(), total, hipMemcpyHostToDevice, s) != hipSuccess) {
+      rc = fail(ISR_EDEVICE, "batch table upload failed");
+      break;
+    }
+    for (int i = 0; i < count && !rc; ++i)
+      if (launch_zero(sn[i].scratch, sn[i].z.zero_bytes, s) != hipSuccess) rc = fail(ISR_EDEVICE, "zero fill failed");
+    if (rc) break;
+    const size_t lds = fbatch_lds(prec);
+    const int grid = c->num_cu * fbatch_resident(prec, lds);
+    if (launch_fbatch(prec, B, grid, lds, s) != hipSuccess) {
+      rc = fail(ISR_EDEVICE, "batch launch failed: %s", hipGetErrorString(hipGetLastError()));
+      break;
+    }
+    for (int i = 0; i < count; ++i)
+      (void)hipMemcpyAsync(sn[i].hs, sn[i].j.st, sizeof(CompState) * fs[i].ncomp, hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(&err_host, B.err, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (hipStreamSynchronize(s) != hipSuccess) {
+      rc = fail(ISR_EDEVICE, "batch failed: %s", hipGetErrorString(hipGetLastError()));
+      break;
+    }
+    if (err_host) rc = fail(ISR_EDEVICE, "batch: a bounded wait expired");
+  } while (0);
+  c->arena->free(tab);
+  if (rc) {
+    cleanup();
+    return rc;
+  }
+  int first = ISR_OK;
+  for (int i = 0; i < count; ++i) {
+    Snap& x = sn[i];
+    const isr_field* f = &fs[i];
+    int flags = 0;
+    bool again = false;
+    for (int k = 0; k < f->ncomp; ++k) {
+      flags |= x.hs[k].flags;
+      if (f->tol >= 0.0 && x.hs[k].rel > f->tol) again = true;
+    }
+    if (flags & ST_MISS) again = true;
+    isr_stats* sti = st ? &st[i] : nullptr;
+    int r = (flags & ST_MISS) ? ISR_OK : status_from_flags(flags);
+    if (r == ISR_OK && again) {
+      c->arena->free(x.scratch);
+      x.scratch = nullptr;
+      c->arena->free(x.b->dev);
+      delete x.b;
+      x.b = nullptr;
+      r = run_compress(c, f, &outs[i], sti);
+    } else if (r == ISR_OK) {
+      isr_blob* b = x.b;
+      isr_stats tmp;
+      std::memset(&tmp, 0, sizeof(tmp));
+      fill_stats(b, x.hs, &tmp);
+      b->status = ISR_OK;
+      const size_t used = 256 + b->bitmap_bytes() + b->ptr_bytes() + b->values_bytes();
+      c->arena->shrink(b->dev, used);
+      b->dev_bytes = (used + 255) & ~size_t(255);
+      tmp.status = ISR_OK;
+      tmp.path = 2;
+      tmp.t_start = t_start;
+      tmp.t_done = now_s();
+      if (sti) *sti = tmp;
+      outs[i] = b;
+      x.b = nullptr;
+    }
+    if (sti) sti->status = r;
+    if (r != ISR_OK && first == ISR_OK) first = r;
+  }
+  cleanup();
+  return first;
+}
+
 int run_batch(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_stats* st) {
   if (count <= 0) return ISR_OK;
-  bool persistent = true;
+  bool persistent = true, stream = true;
   for (int i = 0; i < count; ++i) {
-    const int o = fs[i].order;
-    if ((o != 5 && o != 7 && o != 9) || fs[i].precision != fs[0].precision) persistent = false;
-    // the persistent kernel runs the general passes: their FP32 / BF16
-    // transforms round differently from the streaming ones, so only FP64
-    // batches (exact either way) take it
-    if (fs[i].precision != ISR_PREC_FP64) persistent = false;
+    const int o = fs[i].order, p = fs[i].precision;
+    if ((o != 5 && o != 7 && o != 9) || p != fs[0].precision) persistent = stream = false;
+    // FP64: the persistent kernel of the general passes (exact, so equal to
+    // compressing alone); FP32 / BF16: on request the persistent kernel of the
+    // streaming passes (for the tile shapes it holds), else the concurrent
+    // per-snapshot pipelines
+    if (p != ISR_PREC_FP64) persistent = false;
+    if (p == ISR_PREC_FP64 || !stream || ctx_tile(c, o, p) != fbatch_tile(o)) stream = false;
   }
+  if (stream && (c->flags & ISR_FLAG_BATCH_PERSISTENT)) return run_batch_stream(c, fs, count, outs, st);
   if (!persistent) return run_batch_concurrent(c, fs, count, outs, st);
   const int prec = fs[0].precision;
   hipStream_t s = (hipStream_t)fs[0].stream;

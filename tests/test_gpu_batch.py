@@ -1,7 +1,10 @@
 """One persistent launch over a batch of snapshots (orders 5, 7, 9, uneven
 sizes): every result must equal the same snapshot compressed alone, bit for
-bit (all global sums are exact, so the queue order cannot change them), and
-the FP64 members must equal the oracle."""
+bit (the global sums are exact, or fixed-order per lane with the same grids,
+so the queue order cannot change them), and the FP64 members must equal the
+oracle.  FP32 / BF16 batches run one streaming pipeline per snapshot on the
+scheduler's streams; with FLAG_BATCH_PERSISTENT they run as one persistent
+launch of the streaming path, with the same results."""
 
 import numpy as np
 import pytest
@@ -35,6 +38,16 @@ def test_batch_equals_alone(isr_ctx, prec):
         alone = isr_ctx.compress(u, N, 1e-3, prec)
         same = b.to_bytes() == alone.to_bytes()  # (no assertion diff of MB-sized strings)
         assert same, (N, E)
+    if prec != "fp64":
+        from paper_2407_20731_amd import isr
+        with isr.Context(flags=isr.FLAG_BATCH_PERSISTENT) as ctx2:
+            blobs2 = ctx2.compress_batch([(u, N, 1e-3) for N, E, u in snaps], prec)
+            paths = [b.stats["path"] for b in blobs2]
+            print(f"[batch] {prec} persistent launch, paths {paths}", flush=True)
+            assert paths.count(2) >= len(blobs2) // 2  # reruns alone (window miss, repair) aside
+            for (N, E, u), b, b2 in zip(snaps, blobs, blobs2):
+                same = b.to_bytes() == b2.to_bytes()
+                assert same, (N, E)
 
 
 def test_batch_fp64_matches_oracle(isr_ctx):
