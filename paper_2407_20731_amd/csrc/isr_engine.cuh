@@ -669,7 +669,7 @@ struct PassBLds {
   u64 bm[4][16];
   u32 wp[4][16];
   long long red[4][8];
-  __int128 part[256];
+  __int128 r3[4][3];
   int last;
 };
 
@@ -861,7 +861,7 @@ DEV void passB_body(const Job& j, int comp, int vb, int nvb, PassBLds<N, PREC>& 
   if (!last_block(j.done + D_PASSB * 8 + comp, &L.last, nvb)) return;
   // the component's error total, then its final statistics
   __int128 K[3];
-  for (int k = 0; k < 3; ++k) K[k] = block_total_rows(j.slotsB + (size_t)comp * j.gB * 4, j.gB, 4, k, L.part, tid);
+  block_totals<3>(j.slotsB + (size_t)comp * j.gB * 4, j.gB, 4, K, L.r3, tid);
   if (tid == 0) emit_total(gR, K, PR.m, PR.h, -1);
   __threadfence();
   __syncthreads();

@@ -430,7 +430,7 @@ struct PassBLdsD {
   u64 bal[4][EngD<N, PREC, T>::S + 1];
   u32 wc[4][T * EngD<N, PREC, T>::W];
   long long red[4][8];
-  __int128 part[256];
+  __int128 r3[4][3];
   int last;
 };
 
@@ -559,7 +559,7 @@ DEV void passBD_body(const Job& j, int comp, int vb, int nvb, PassBLdsD<N, PREC,
   if (tid < 3) j.slotsB[((size_t)comp * j.gB + vb) * 4 + tid] = L.red[0][tid];
   if (!last_block(j.done + D_PASSB * 8 + comp, &L.last, nvb)) return;
   __int128 K[3];
-  for (int k = 0; k < 3; ++k) K[k] = block_total_rows(j.slotsB + (size_t)comp * j.gB * 4, j.gB, 4, k, L.part, tid);
+  block_totals<3>(j.slotsB + (size_t)comp * j.gB * 4, j.gB, 4, K, L.r3, tid);
   if (tid == 0) emit_total(gR, K, PR.m, PR.h, -1);
   __threadfence();
   __syncthreads();

@@ -358,7 +358,7 @@ struct PassBLdsL {
   u32 wp[4][EngL<N, PREC>::W];
   TabLdsL<EngL<N, PREC>::n3> tab;
   long long red[4][8];
-  __int128 part[256];
+  __int128 r3[4][3];
   int last;
 };
 
@@ -499,7 +499,7 @@ __global__ __launch_bounds__(256, 2) void k_passBL(Job j) {
   if (tid < 3) j.slotsB[((size_t)comp * j.gB + blockIdx.x) * 4 + tid] = L.red[0][tid];
   if (!last_block(j.done + D_PASSB * 8 + comp, &L.last, gridDim.x)) return;
   __int128 K[3];
-  for (int k = 0; k < 3; ++k) K[k] = block_total_rows(j.slotsB + (size_t)comp * j.gB * 4, j.gB, 4, k, L.part, tid);
+  block_totals<3>(j.slotsB + (size_t)comp * j.gB * 4, j.gB, 4, K, L.r3, tid);
   if (tid == 0) emit_total(gR, K, PR.m, PR.h, -1);
   __threadfence();
   __syncthreads();

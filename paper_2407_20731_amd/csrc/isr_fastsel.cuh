@@ -35,13 +35,12 @@ DEV void refsel_body(const Job& j, int comp, int L, int vb, int nvb, RefselLds& 
 // into bin win_hi; the last workgroup runs the level-1 selection.
 struct GatherLds {
   u64 red[4][9];
-  __int128 part[256];
+  __int128 r7[4][7], r9[4][9];
   int last;
 };
 
 DEV void gather_body(const Job& j, int comp, int vb, int nvb, GatherLds& X) {
   u64(&red)[4][9] = X.red;
-  __int128* part = X.part;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   CompState* st = j.st + comp;
   if (st->flags & ST_MISS) return;
@@ -72,25 +71,23 @@ DEV void gather_body(const Job& j, int comp, int vb, int nvb, GatherLds& X) {
   if (tid < 9) j.gslot[((size_t)comp * GATHER_GMAX + vb) * 16 + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
   if (vb == 0) {
     // totals of pass A's workgroup sums: fields 0..2 norm, 3..5 energy, 6 count
-    for (int f = 0; f < 7; ++f) {
-      const __int128 t = block_total_rows(j.slotsA + (size_t)comp * j.gA * 8, j.gA, 8, f, part, tid);
-      if (tid == 0) red[0][f] = (u64)t, red[1][f] = (u64)((unsigned __int128)t >> 64);
-      __syncthreads();
-    }
+    __int128 T[7];
+    block_totals<7>(j.slotsA + (size_t)comp * j.gA * 8, j.gA, 8, T, X.r7, tid);
     if (tid == 0) {
       __int128 K[3];
-      for (int k = 0; k < 3; ++k) K[k] = (__int128)(((unsigned __int128)red[1][k] << 64) | red[0][k]);
+      for (int k = 0; k < 3; ++k) K[k] = T[k];
       emit_total(gN, K, st->xm_norm, j.xh, -1);
-      for (int k = 0; k < 3; ++k) K[k] = (__int128)(((unsigned __int128)red[1][3 + k] << 64) | red[0][3 + k]);
+      for (int k = 0; k < 3; ++k) K[k] = T[3 + k];
       if (wlo < whi) emit_total(gE, K, wlo - 1023, j.xh, wlo - 1);
-      const u64 above = red[0][6];
+      const u64 above = (u64)T[6];
       if (above) atomicAdd(&gE[whi].cnt, above);
     }
   }
   if (!last_block(j.done + D_GATHER * 8 + comp, &X.last, nvb)) return;
+  __int128 T9[9];
+  block_totals<9>((const long long*)j.gslot + (size_t)comp * GATHER_GMAX * 16, nvb, 16, T9, X.r9, tid);
   for (int k = 0; k < 9; ++k) {
-    const u64 w = (u64)block_total_rows((const long long*)j.gslot + (size_t)comp * GATHER_GMAX * 16, nvb, 16,
-                                        k, part, tid);
+    const u64 w = (u64)T9[k];
     const int b = wlo + k / 3;
     if (tid == 0 && w && b < whi) {
       if (k % 3 == 0) atomicAdd(&gE[b].cnt, w);

@@ -216,21 +216,39 @@ DEV void block_sum_i64(long long (&v)[CNT], long long (*red)[8], int tid) {
   __syncthreads();
 }
 
-// Workgroup of 256: total of field f over `count` rows of `stride` 64-bit
-// signed values starting at base (row r, field f at base[r * stride + f]), as
-// a 128-bit integer in thread 0.  part: 256 __int128 of LDS.
-DEV __int128 block_total_rows(const long long* base, int count, int stride, int f, __int128* part, int tid) {
-  __int128 p = 0;
-  for (int r = tid; r < count; r += 256) p += (__int128)base[(size_t)r * stride + f];
-  part[tid] = p;
-  __syncthreads();
-  for (int d = 128; d > 0; d >>= 1) {
-    if (tid < d) part[tid] += part[tid + d];
-    __syncthreads();
+DEV __int128 shfl_xor128(__int128 v, int m) {
+  const unsigned __int128 u = (unsigned __int128)v;
+  const u64 lo = shfl_xor64((u64)u, m), hi = shfl_xor64((u64)(u >> 64), m);
+  return (__int128)(((unsigned __int128)hi << 64) | lo);
+}
+
+// Workgroup of 256: totals of fields 0..F-1 over `count` rows of `stride`
+// 64-bit signed values starting at base (row r, field f at base[r * stride +
+// f]), as 128-bit integers, in every thread.  Every field of a row is loaded
+// at once, so the workgroup waits for memory once.  red: [4][F] of LDS.
+template <int F>
+DEV void block_totals(const long long* base, int count, int stride, __int128 (&tot)[F], __int128 (*red)[F], int tid) {
+  const int lane = tid & 63, wv = tid >> 6;
+  __int128 p[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) p[f] = 0;
+  for (int r = tid; r < count; r += 256) {
+    long long v[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) v[f] = base[(size_t)r * stride + f];
+#pragma unroll
+    for (int f = 0; f < F; ++f) p[f] += (__int128)v[f];
   }
-  const __int128 t = part[0];
+#pragma unroll
+  for (int f = 0; f < F; ++f)
+    for (int m = 32; m > 0; m >>= 1) p[f] += shfl_xor128(p[f], m);
+  if (lane == 0)
+#pragma unroll
+    for (int f = 0; f < F; ++f) red[wv][f] = p[f];
   __syncthreads();
-  return t;
+#pragma unroll
+  for (int f = 0; f < F; ++f) tot[f] = red[0][f] + red[1][f] + red[2][f] + red[3][f];
+  __syncthreads();
 }
 
 // Last workgroup of a component to finish (returns true in every thread of
