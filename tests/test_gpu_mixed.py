@@ -55,16 +55,18 @@ def test_mixed_against_oracle(isr_ctx, prec, order, E, tol):
     check_mixed(isr_ctx, prec, order, E, tol, seed=200 + order)
 
 
-def check_mixed(isr_ctx, prec, order, E, tol, seed):
-    """Every property listed in the module docstring, for one request."""
+def check_mixed(isr_ctx, prec, order, E, tol, seed, jac_np=None):
+    """Every property listed in the module docstring, for one request (with
+    per-element Jacobians when jac_np is given)."""
     n = order + 1
     u_np = synth.field(E, order, seed=seed)
     u = torch.from_numpy(u_np).cuda()
-    blob = isr_ctx.compress(u, order, tol, prec)
+    jac = torch.from_numpy(jac_np).cuda() if jac_np is not None else None
+    blob = isr_ctx.compress(u, order, tol, prec, jac=jac)
     coef = isr_ctx.forward(u, order, prec).cpu().numpy().astype(np.float64)
     torch.cuda.synchronize()
     arr = blob.arrays()
-    ref = oracle.compress(u_np, order, tol, keep_arrays=True)
+    ref = oracle.compress(u_np, order, tol, jac=jac_np, keep_arrays=True)
     assert arr.value_bytes == 4
     emax = np.abs(u_np).reshape(u_np.shape[0], E, -1).max(axis=2)  # [comp, E]
     report = []
@@ -81,6 +83,8 @@ def check_mixed(isr_ctx, prec, order, E, tol, seed):
         if np.any(diff):
             # energy perturbation allowed by the coefficient bound at tau's scale
             g3 = np.broadcast_to(gll_tables(order).g3, rc.coef.shape)
+            if jac_np is not None:
+                g3 = jac_np[:, None, None, None] * g3
             cabs = np.sqrt(rc.tau / g3)
             beta = 2 * bound / cabs + (bound / cabs) ** 2
             band = np.abs(rc.energy - rc.tau) <= 2 * beta * rc.tau
@@ -95,7 +99,7 @@ def check_mixed(isr_ctx, prec, order, E, tol, seed):
         rec = oracle.decompress(arr.bitmap[c], arr.values[c].astype(np.float64), order)
         from oracle.compress import norm_terms
         from oracle.exact import exact_sum
-        err2 = exact_sum(norm_terms(u_np[c] - rec, gll_tables(order).w3, None))
+        err2 = exact_sum(norm_terms(u_np[c] - rec, gll_tables(order).w3, jac_np))
         rel_blob = math.sqrt(err2 / rc.U2)
         # the blob's FP64 reconstruction differs from the reduced-precision one
         # the kernel measured by the inverse transform error only

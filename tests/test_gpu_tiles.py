@@ -76,3 +76,18 @@ def test_autotune_round_trip(tmp_path):
     with isr.Context(autotune_path=path) as ctx2:
         assert ctx2.get_tile(5, "bf16") == rep["best"]
         assert ctx2.get_tile(5, "fp32") in SHAPES[5]  # untouched entry: the built-in choice
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("order,tile", [(3, 8), (5, 2), (5, 4), (7, 0), (7, 1), (9, 0), (9, 1), (11, 1)])
+def test_tile_shape_with_jacobians(isr_ctx, prec, order, tile):
+    """Per-element Jacobians (affine elements of different sizes) on the
+    streaming engines: the norm, energy and error terms carry J_e."""
+    E = elements_for(order, tile)
+    jac = np.random.default_rng(order + tile).uniform(0.1, 3.0, size=E)
+    print(f"[case] prec={prec} order={order} tile={tile} E={E} with Jacobians", flush=True)
+    isr_ctx.set_tile(order, prec, tile)
+    try:
+        check_mixed(isr_ctx, prec, order, E, 1e-3, seed=400 + order, jac_np=jac)
+    finally:
+        isr_ctx.set_tile(order, prec, -1)
