@@ -333,13 +333,20 @@ DEV void passAD_body(const Job& j, int comp, int vb, int nvb, PassALdsD<N, PREC,
     const long long e0 = t * T;
     const int ne = (int)((E - e0) < T ? (E - e0) : T), nv = ne * n3;
     const double* tile = ub + e0 * n3;
-    // field values in, exact norm terms on the way
-#pragma unroll 2
+    // field values in (every load of the tile issued before the first is
+    // used: one memory latency per tile), exact norm terms on the way
+    double ut[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int v = 64 * s + lane;
+      ut[s] = v < nv ? __builtin_nontemporal_load(tile + v) : 0.0;
+    }
+#pragma unroll
     for (int s = 0; s < S; ++s) {
       const int v = 64 * s + lane;
       int e, f;
       dense_ef<G>(v, e, f);
-      const double u = v < nv ? __builtin_nontemporal_load(tile + v) : 0.0;
+      const double u = ut[s];
       const double x = v < nv ? (j.jac ? j.jac[e0 + e] * L.tab.w3[f] : L.tab.w3[f]) * (u * u) : 0.0;
       const double r = xadd_r(an, PN, x);
       if (r != 0.0) slow_bin(gN, r);
