@@ -227,7 +227,11 @@ void isr_blob_free(isr_blob *b);
  * the dense-tile engine: a wavefront owns T consecutive elements and does all
  * per-value work (norm, energies, window tests, keep decisions, bitmaps,
  * ranks, error terms) in dense order.  Every shape meets the same bound and
- * passes the same checks; the choice only changes speed.  The table starts
+ * passes the same checks.  The transforms agree bit for bit, but the FP32 /
+ * BF16 energy and error sums add each lane's terms in that lane's order, so
+ * two shapes can differ in the last bits of S and err2 (and then in
+ * coefficients at the threshold); one shape always gives the same result.
+ * The table starts
  * from the built-in choice, or from config.autotune_path when that file
  * exists (text lines "order precision tile"). */
 typedef struct {
@@ -250,8 +254,9 @@ int isr_set_tile(isr_ctx *ctx, int32_t order, int32_t precision, int32_t tile);
  * f->precision), one warm-up call and then the best of `reps` timed calls
  * each, keep the fastest in the table and, when config.autotune_path was
  * given, rewrite that file with the whole table.  f should look like the
- * production snapshots (its size matters).  rep may be NULL.  Errors: as
- * isr_compress; ISR_EINVAL for FP64 (it has one shape). */
+ * production snapshots (its size matters).  Requests of the same (order,
+ * precision) submitted meanwhile may run with a candidate shape.  rep may be
+ * NULL.  Errors: as isr_compress; ISR_EINVAL for FP64 (it has one shape). */
 int isr_autotune(isr_ctx *ctx, const isr_field *f, int32_t reps, isr_tune_report *rep);
 
 /* Host-only: the library's own FP64 tables for order N (each entry the
