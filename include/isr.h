@@ -227,10 +227,10 @@ void isr_blob_free(isr_blob *b);
  * the dense-tile engine: a wavefront owns T consecutive elements and does all
  * per-value work (norm, energies, window tests, keep decisions, bitmaps,
  * ranks, error terms) in dense order.  Every shape meets the same bound and
- * passes the same checks.  The transforms agree bit for bit, but the FP32 /
- * BF16 energy and error sums add each lane's terms in that lane's order, so
- * two shapes can differ in the last bits of S and err2 (and then in
- * coefficients at the threshold); one shape always gives the same result.
+ * passes the same checks, and one shape always gives the same result; but
+ * the FP32 / BF16 energy and error sums add each lane's terms in that lane's
+ * order, so two shapes can differ in the last bits of S and err2 (and then in
+ * coefficients at the threshold).
  * The table starts
  * from the built-in choice, or from config.autotune_path when that file
  * exists (text lines "order precision tile"). */
