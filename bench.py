@@ -144,11 +144,33 @@ def cpu_baseline() -> dict:
     u = synth.field(CPU_SAMPLE_ELEMS, ORDER, ncomp=NCOMP, seed=SEED)
     with threadpool_limits(limits=1):  # one core, whatever BLAS would pick
         t0 = time.perf_counter()
-        oracle.compress(u, ORDER, TOL)
+        ref = oracle.compress(u, ORDER, TOL, keep_arrays=True)  # (keeping the arrays costs nothing)
         dt = time.perf_counter() - t0
     return {"value": u.nbytes / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"{CPU_SAMPLE_ELEMS} of the 65,536 elements (same generator, N=7, 3 components, "
-                      f"tol 1e-3), full oracle pipeline (FP64 NumPy, one thread), {dt:.1f} s"}
+                      f"tol 1e-3), full oracle pipeline (FP64 NumPy, one thread), {dt:.1f} s"}, ref, u
+
+
+def against_oracle(gpu: dict, ref, u) -> dict:
+    """Per precision and component: the GPU result against the FP64 oracle's on the same snapshot."""
+    import numpy as np
+    out = {}
+    for p, (arr, rec) in gpu.items():
+        rows = []
+        for c, rc in enumerate(ref.comps):
+            h = arr.comps[c]
+            d = rec[c] - rc.recon
+            row = {"kept": int(h["kept"]), "kept_oracle": int(rc.kept), "tau_rel_diff": float(h["tau"] / rc.tau - 1.0),
+                   "rel_err": float(h["rel_err"]), "rel_err_oracle": float(rc.rel_err),
+                   "U2_equal": bool(h["U2"] == rc.U2),
+                   "recon_rel_l2_vs_oracle": float(np.sqrt(np.sum(d * d) / np.sum(u[c] * u[c])))}
+            if p == "fp64":
+                row["bit_exact"] = bool(h["tau"] == rc.tau and np.array_equal(arr.bitmap[c], rc.bitmap) and
+                                        np.array_equal(arr.values[c].view(np.uint64), rc.values.view(np.uint64)) and
+                                        np.array_equal(rec[c].view(np.uint64), rc.recon.view(np.uint64)))
+            rows.append(row)
+        out[p] = rows
+    return out
 
 
 def time_single(ctx, u, prec, steps, warmup, stream, order=ORDER):
@@ -386,6 +408,14 @@ def main() -> int:
     }
     if "fp64" in results and head != "fp64":
         out["speedup_vs_fp64"] = results["fp64"]["ms"] / r["ms"]
+    gpu_res = {}
+    if not args.no_cpu and (E, N) == (CPU_SAMPLE_ELEMS, ORDER):
+        # one more (untimed) result per precision, kept on the host for the
+        # comparison with the oracle's result on the same snapshot
+        for p in precs:
+            b = ctx.compress(u, N, TOL, p, stream=stream)
+            gpu_res[p] = (b.arrays(), ctx.decompress(b).cpu().numpy())
+            b.free()
     ctx.close()
     if not (args.no_batch and args.no_serving):
         log("generating element pools on the device (500k elements per order)")
@@ -416,7 +446,10 @@ def main() -> int:
         del pool
     if not args.no_cpu:
         log("timing the CPU oracle sample")
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"], ref, u_host = cpu_baseline()
+        if gpu_res:
+            out["vs_oracle"] = against_oracle(gpu_res, ref, u_host)
+            log(f"against the oracle: {out['vs_oracle']}")
     print(json.dumps(out), flush=True)
     return 0
 
