@@ -435,11 +435,11 @@ def main() -> int:
                 out["batch"] = run_batch(bctx, pool, head)
                 log(f"batch: {out['batch']}")
             if head != "fp64":
-                # the same batch as one persistent launch of the streaming path
+                # the same batch as one streaming pipeline per snapshot on the scheduler's streams
                 with isr.Context(device=0, budget_bytes=128 << 30, autotune_path=tune_path,
-                                 flags=isr.FLAG_BATCH_PERSISTENT) as pctx:
-                    out["batch_persistent"] = run_batch(pctx, pool, head)
-                    log(f"batch, one persistent launch: {out['batch_persistent']}")
+                                 flags=isr.FLAG_BATCH_STREAMS) as pctx:
+                    out["batch_streams"] = run_batch(pctx, pool, head)
+                    log(f"batch, per-snapshot pipelines on streams: {out['batch_streams']}")
         if not args.no_serving:
             out["serving"] = run_serving(pool, "fp32", 64 << 30, args.serving_requests, 0.7, tune_path)
             log(f"serving: {out['serving']}")

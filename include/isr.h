@@ -66,9 +66,8 @@ extern "C" {
 
 /* ---- context flags ---------------------------------------------------- */
 #define ISR_FLAG_TIMING 1u  /* record device time per phase into isr_stats */
-#define ISR_FLAG_BATCH_PERSISTENT 2u /* FP32/BF16 batches of orders 5/7/9: one persistent launch of
-                                        the streaming path; default: one streaming pipeline per
-                                        snapshot on the scheduler's streams (faster today) */
+#define ISR_FLAG_BATCH_STREAMS 2u /* FP32/BF16 batches: one streaming pipeline per snapshot on the
+                                     scheduler's streams instead of one persistent launch */
 
 #define ISR_MAX_COMP 8
 #define ISR_MAX_ORDER 15
@@ -170,7 +169,10 @@ const char *isr_last_error(void);
 int isr_compress(isr_ctx *ctx, const isr_field *f, isr_blob **out, isr_stats *st);
 
 /* Compress several snapshots (orders may differ) in one batched launch
- * sequence.  outs[i] / st[i] as in isr_compress; returns the first non-OK
+ * sequence: one persistent launch when every snapshot has order 5, 7 or 9
+ * (FP32 / BF16: with the tile shapes the persistent kernel holds, the
+ * built-in ones, and at least 8 snapshots), else one pipeline per snapshot on
+ * the scheduler's streams.  outs[i] / st[i] as in isr_compress; returns the first non-OK
  * status (each st[i].status holds its own).  Footprint of the whole batch must
  * fit the budget (ISR_ENOMEM otherwise). */
 int isr_compress_batch(isr_ctx *ctx, const isr_field *fs, int32_t count, isr_blob **outs,

@@ -267,6 +267,7 @@ enum FastBatchPhase {
 };
 static_assert(NFQ <= NPH, "phase offsets of BatchCtl");
 inline int fbatch_tile(int order) { return order == 5 ? 4 : order == 7 ? 0 : order == 9 ? 1 : -1; }
+constexpr int FBATCH_MIN = 8;  // smallest FP32 / BF16 batch that takes the persistent launch
 hipError_t launch_fbatch(int precision, const BatchCtl& B, int grid, size_t lds_bytes, hipStream_t s);
 size_t fbatch_lds(int precision);
 int fbatch_resident(int precision, size_t lds_bytes);

@@ -1001,13 +1001,16 @@ int run_batch(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_s
     const int o = fs[i].order, p = fs[i].precision;
     if ((o != 5 && o != 7 && o != 9) || p != fs[0].precision) persistent = stream = false;
     // FP64: the persistent kernel of the general passes (exact, so equal to
-    // compressing alone); FP32 / BF16: on request the persistent kernel of the
-    // streaming passes (for the tile shapes it holds), else the concurrent
+    // compressing alone); FP32 / BF16: the persistent kernel of the streaming
+    // passes (for the tile shapes it holds), or on request the concurrent
     // per-snapshot pipelines
     if (p != ISR_PREC_FP64) persistent = false;
     if (p == ISR_PREC_FP64 || !stream || ctx_tile(c, o, p) != fbatch_tile(o)) stream = false;
   }
-  if (stream && (c->flags & ISR_FLAG_BATCH_PERSISTENT)) return run_batch_stream(c, fs, count, outs, st);
+  // (a handful of snapshots keeps the phases of one snapshot apart in the
+  // queue and leaves most workgroups waiting: their own pipelines are faster)
+  if (stream && count >= FBATCH_MIN && !(c->flags & ISR_FLAG_BATCH_STREAMS))
+    return run_batch_stream(c, fs, count, outs, st);
   if (!persistent) return run_batch_concurrent(c, fs, count, outs, st);
   const int prec = fs[0].precision;
   hipStream_t s = (hipStream_t)fs[0].stream;

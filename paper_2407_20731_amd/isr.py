@@ -29,7 +29,7 @@ LIB_PATH = os.path.join(_HERE, "libisr.so")
 OK, PENDING, EINVAL, ENOMEM, EDEVICE, ETOL, ECANCELED, ENOTFOUND = 0, 1, -1, -2, -3, -4, -5, -6
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 FLAG_TIMING = 1
-FLAG_BATCH_PERSISTENT = 2  # FP32/BF16 batches of orders 5/7/9 as one persistent launch of the streaming path
+FLAG_BATCH_STREAMS = 2  # FP32/BF16 batches on the scheduler's streams instead of one persistent launch
 MAX_COMP = 8
 NPHASE = 8
 PHASES = ("pass1", "select1", "pass2", "refine", "pass3", "finalize", "repair", "fallback")
