@@ -40,26 +40,36 @@ FP64_NOFMA_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
 
 E_BENCH, ORDER, NCOMP, TOL, SEED = 65536, 7, 3, 1e-3, 2
 CPU_SAMPLE_ELEMS = 65536
-# HBM bytes of the compaction pass measured by rocprofv3 counters (committed
-# summary); reported only while the kernel sources are the ones measured
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "passB_bf16_n7_65536_traffic.txt")
-KERNEL_NAMES = {"pass1": "k_sample + k_passA", "pass3": "k_passB"}
+# HBM bytes of the two streaming passes measured by rocprofv3 counters
+# (committed summary); reported only while the kernel sources are the ones
+# measured
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "streaming_bf16_n7_65536_traffic.txt")
+KERNEL_NAMES = {"pass1": "k_passA", "pass3": "k_passB"}
+TRAFFIC_KERNELS = {"pass1": "void isr::k_passA<7, 2>", "pass3": "void isr::k_passB<7, 2>"}
+TRAFFIC_SOURCES = ["isr_common.cuh", "isr_engine.cuh", "isr_fastsel.cuh", "isr_internal.h", "isr_passes.cuh",
+                   "isr_selbody.cuh", "isr_xsum.cuh", "isr_pass_bf16.hip"]
 
 
-def measured_traffic(prec: str):
+def _sources_sha(files) -> str:
     import hashlib
+    h = hashlib.sha256()
+    for name in files:
+        with open(os.path.join(ROOT, "paper_2407_20731_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(prec: str, phase: str):
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if prec != "bf16":
+    if prec != "bf16" or phase not in rec.get("kernels", {}):
         return None
-    h = hashlib.sha256()
-    for name in rec.get("source_files", []):
-        with open(os.path.join(ROOT, "paper_2407_20731_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    return rec["traffic_bytes"] if h.hexdigest() == rec.get("source_sha256") else None
+    if _sources_sha(rec.get("source_files", [])) != rec.get("source_sha256"):
+        return None
+    return rec["kernels"][phase]["traffic_bytes"]
 DTYPES = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
 
 
@@ -77,24 +87,23 @@ def _counter_kib(csv_path: str, kernel: str, counter: str) -> float:
 
 
 def summarize_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib, commands) -> dict:
-    """HBM bytes of the compaction pass from two rocprofv3 --pmc runs, scaled by
-    what the same counters read for a plain device copy of copy_mib MiB."""
-    import hashlib
-    kern, copyk = "void isr::k_passB<7, 2>", "__amd_rocclr_copyBuffer"
+    """HBM bytes of the two streaming passes (pass A, pass B) from two rocprofv3
+    --pmc runs, scaled by what the same counters read for a plain device copy
+    of copy_mib MiB."""
+    copyk = "__amd_rocclr_copyBuffer"
     moved = copy_mib * 1024.0  # KiB read, and KiB written, per copy
     ff = moved / _counter_kib(copy_fetch_csv, copyk, "FETCH_SIZE")
     fw = moved / _counter_kib(copy_write_csv, copyk, "WRITE_SIZE")
-    fetch = _counter_kib(fetch_csv, kern, "FETCH_SIZE")
-    write = _counter_kib(write_csv, kern, "WRITE_SIZE")
-    files = ["isr_common.cuh", "isr_engine.cuh", "isr_internal.h", "isr_passes.cuh", "isr_selbody.cuh", "isr_xsum.cuh"]
-    h = hashlib.sha256()
-    for name in files:
-        with open(os.path.join(ROOT, "paper_2407_20731_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    return {"kernel": "k_passB<7, BF16>", "workload": "65,536 elements, N=7, 3 FP64 components, tol 1e-3",
-            "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write, "copy_factor_fetch": ff,
-            "copy_factor_write": fw, "traffic_bytes": (fetch * ff + write * fw) * 1024.0,
-            "source_files": files, "source_sha256": h.hexdigest(), "commands": commands}
+    kernels = {}
+    for phase, kern in TRAFFIC_KERNELS.items():
+        fetch = _counter_kib(fetch_csv, kern, "FETCH_SIZE")
+        write = _counter_kib(write_csv, kern, "WRITE_SIZE")
+        kernels[phase] = {"kernel": kern.replace("void isr::", "").replace(", 2>", ", BF16>"),
+                          "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write,
+                          "traffic_bytes": (fetch * ff + write * fw) * 1024.0}
+    return {"workload": "65,536 elements, N=7, 3 FP64 components, tol 1e-3", "kernels": kernels,
+            "copy_factor_fetch": ff, "copy_factor_write": fw, "source_files": TRAFFIC_SOURCES,
+            "source_sha256": _sources_sha(TRAFFIC_SOURCES), "commands": commands}
 
 
 def summarize_trace(trace_csv: str, title: str, command: str) -> str:
@@ -117,6 +126,31 @@ def summarize_trace(trace_csv: str, title: str, command: str) -> str:
             continue
         out.append(f"| `{k}` | {len(v)} | {sum(v) / len(v):.1f} | {min(v):.1f} | {max(v):.1f} | "
                    f"{100 * sum(v) / tot:.1f} % |")
+    return "\n".join(out) + "\n"
+
+
+def summarize_counters(csv_paths, title: str, commands) -> str:
+    """Markdown table of rocprofv3 --pmc counters (averaged per dispatch) for the library's kernels."""
+    import csv
+    per = {}
+    for path in csv_paths:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                k = r["Kernel_Name"]
+                if "isr::" not in k:
+                    continue
+                d = per.setdefault(k, {}).setdefault(r["Counter_Name"], {})
+                d[r["Dispatch_Id"]] = d.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    names = sorted({c for v in per.values() for c in v})
+    out = [f"# {title}", "", "Commands (GPU box, repository root):", ""] + [f"    {c}" for c in commands] + [
+        "", "Per dispatch, averaged over the dispatches of each kernel (device totals; SQ_*_CYCLES in the "
+        "counters' own units).", "", "| Kernel | " + " | ".join(names) + " |", "|---" * (len(names) + 1) + "|"]
+    for k in sorted(per, key=lambda k: -per[k].get("SQ_INSTS_VALU", {0: 0}).get(min(per[k].get("SQ_INSTS_VALU", {0: 0})), 0)):
+        row = []
+        for c in names:
+            v = per[k].get(c)
+            row.append(f"{sum(v.values()) / len(v):.3g}" if v else "")
+        out.append(f"| `{k}` | " + " | ".join(row) + " |")
     return "\n".join(out) + "\n"
 
 
@@ -313,7 +347,14 @@ def main() -> int:
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="write the compaction pass's HBM traffic file from four rocprofv3 --pmc runs (no GPU)")
     ap.add_argument("--traffic-commands", nargs="*", default=[], help="the commands of those four runs")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="CSV",
+                    help="print a markdown table of rocprofv3 --pmc counters per kernel (no GPU); "
+                         "title and commands from --counters-title / --traffic-commands")
+    ap.add_argument("--counters-title", default="Counters")
     args = ap.parse_args()
+    if args.summarize_counters:
+        print(summarize_counters(args.summarize_counters, args.counters_title, args.traffic_commands), end="")
+        return 0
     if args.summarize_trace:
         print(summarize_trace(*args.summarize_trace), end="")
         return 0
@@ -363,9 +404,17 @@ def main() -> int:
         elif not args.no_tune:
             tuning[p] = ctx.autotune(u, N, TOL, p, reps=2)
             log(f"autotune N={N} {p}: {tuning[p]}")
+    # the timed steps run on a context without per-phase timing events (each
+    # event adds a few microseconds between kernels); the phase table comes
+    # from the timing context, on the same tile shapes
+    ctx_run = isr.Context(device=0, autotune_path=tune_path)
+    for p in precs:
+        if p != "fp64":
+            ctx_run.set_tile(N, p, ctx.get_tile(N, p))
     for p in precs:
         steps = args.steps if p != "fp64" or args.precision == "fp64" else max(2, args.steps // 3)
-        results[p] = time_single(ctx, u, p, steps, args.warmup, stream, N)
+        results[p] = time_single(ctx_run, u, p, steps, args.warmup, stream, N)
+        results[p]["phase_ms"] = time_single(ctx, u, p, max(2, min(steps, 5)), 1, stream, N)["phase_ms"]
         log(f"{p}: {results[p]['ms']:.3f} ms/step, phases {results[p]['phase_ms']}")
     if args.precision == "auto":
         ok = [p for p in ("bf16", "fp32") if results[p]["status"] == [0] and results[p]["max_rel"] <= TOL]
@@ -380,12 +429,13 @@ def main() -> int:
         flops = flops_per_value(dom, n) * nvals
         achieved = flops / (avg[dom] / 1e3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": FP64_NOFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_NOFMA_PEAK_TFLOPS, "traffic": None, "kernel": dom, "kernel_ms": avg[dom]}
+                "frac": achieved / FP64_NOFMA_PEAK_TFLOPS, "traffic": None, "kernel": KERNEL_NAMES.get(dom, dom),
+                "kernel_ms": avg[dom]}
     else:
         byts = nvals * 8 + (r["blob_bytes"] if dom == "pass3" else 0)
         achieved = byts / (avg[dom] / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(head) if dom == "pass3" and (E, N) == (E_BENCH, ORDER) else None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(head, dom) if (E, N) == (E_BENCH, ORDER) and ctx.get_tile(N, head) == 0 else None,
                 "kernel": KERNEL_NAMES.get(dom, dom), "kernel_ms": avg[dom], "algorithmic_bytes_per_launch": byts}
     # whole-path algorithmic traffic: two field reads plus the blob, per step
     algo = 2 * nvals * 8 + r["blob_bytes"]
@@ -417,6 +467,7 @@ def main() -> int:
             gpu_res[p] = (b.arrays(), ctx.decompress(b).cpu().numpy())
             b.free()
     ctx.close()
+    ctx_run.close()
     if not (args.no_batch and args.no_serving):
         log("generating element pools on the device (500k elements per order)")
         pool = pools((5, 7, 9), 500000)

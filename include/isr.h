@@ -71,7 +71,7 @@ extern "C" {
 
 #define ISR_MAX_COMP 8
 #define ISR_MAX_ORDER 15
-#define ISR_NPHASE 8
+#define ISR_NPHASE 9
 
 typedef struct isr_ctx isr_ctx;
 typedef struct isr_blob isr_blob;
@@ -137,7 +137,9 @@ typedef struct {
                                     0 norm+histogram pass, 1 threshold select,
                                     2 candidate pass, 3 refine, 4 compact+verify
                                     pass, 5 finalize, 6 repair total, 7 an
-                                    abandoned streaming attempt (see path) */
+                                    abandoned streaming attempt (see path),
+                                    8 zero fill and sampling pass with its
+                                    window selection (ahead of phase 0) */
   int32_t repair_iters;
   int32_t status;
   int32_t precision;

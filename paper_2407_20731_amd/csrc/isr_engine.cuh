@@ -37,6 +37,7 @@
 #pragma once
 
 #include "isr_passes.cuh"
+#include "isr_fastsel.cuh"
 #include "isr_selbody.cuh"
 #include "isr_xsum.cuh"
 
@@ -347,82 +348,8 @@ struct SampleLds {
   int last;
 };
 
-// One wave per component: window [b - 1, b + 2) around the bin b where the
-// rounded cumulative sampled energy first exceeds tol^2 * (sampled U2), and
-// the norm-term bound 2^(largest sampled exponent + 8).
-DEV void select_sample_body(const Job& j, int comp) {
-  const int lane = lane_id();
-  CompState* st = j.st + comp;
-  const HistBin* H = j.histEs + (size_t)comp * HBINS;
-  if (lane == 0) {
-    const int mx = st->samp_maxe;  // biased; 0 when every sampled term is 0
-    int m = mx - 1023 + 8;
-    m = m < XM_MIN ? XM_MIN : (m > XM_MAX ? XM_MAX : m);
-    st->xm_norm = m;
-    st->win_mode = 1;
-  }
-  const double tol = j.tol;
-  if (tol < 0.0) {  // keep everything: no window, every energy counts as "above"
-    if (lane == 0) st->win_lo = st->win_hi = 0;
-    return;
-  }
-  const double B = (tol * tol) * st->samp_u2;
-  double cs = 0.0;
-  u64 cc = 0;
-  for (int k = 0; k < 32; ++k) {
-    const int b = 32 * lane + k;
-    if (b < HBINS - 1) {
-      cs += __longlong_as_double((long long)H[b].lo);
-      cc += H[b].cnt;
-    }
-  }
-  double incl = cs;
-  for (int d = 1; d < 64; d <<= 1) {
-    const double o = __shfl_up(incl, d);
-    if (lane >= d) incl += o;
-  }
-  const u64 over = ballot(incl > B);
-  const u64 nonempty = ballot(cc != 0ull);
-  int bstar = -1;
-  if (over) {
-    const int fl = __ffsll((long long)over) - 1;
-    double cum = __shfl(incl - cs, fl);
-    for (int k = 0; k < 32; ++k) {
-      const int b = 32 * fl + k;
-      if (b >= HBINS - 1) break;
-      cum += __longlong_as_double((long long)H[b].lo);
-      if (cum > B) {
-        bstar = b;
-        break;
-      }
-    }
-  } else if (nonempty) {
-    // every sampled energy fits the budget: the top bin (tau is likely +inf,
-    // which the general pipeline handles)
-    const int fl = 63 - __clzll((long long)nonempty);
-    for (int k = 31; k >= 0; --k) {
-      const int b = 32 * fl + k;
-      if (b < HBINS - 1 && H[b].cnt) {
-        bstar = b;
-        break;
-      }
-    }
-  }
-  if (lane == 0) {
-    const int wl = bstar - 1 < 1 ? 1 : bstar - 1;
-    const int wh = bstar + 2 > HBINS - 2 ? HBINS - 2 : bstar + 2;
-    if (bstar < 0 || wl - 1023 < XM_MIN || wl >= wh) {
-      st->flags |= ST_MISS;
-      st->resolved = 1;
-    } else {
-      st->win_lo = wl;
-      st->win_hi = wh;
-    }
-  }
-}
-
 template <int N, int PREC>
-DEV void sample_body(const Job& j, int comp, int vb, int nvb, SampleLds<N, PREC>& L) {
+DEV void sample_body(const Job& j, int comp, int vb, int nvb, SampleLds<N, PREC>& L, bool tail) {
   typedef Eng<N, PREC> G;
   constexpr int n3 = G::n3, NS = G::NS, EPW = G::EPW;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -492,14 +419,14 @@ DEV void sample_body(const Job& j, int comp, int vb, int nvb, SampleLds<N, PREC>
     atomicAdd(&st->samp_u2, L.u2[0] + L.u2[1] + L.u2[2] + L.u2[3]);
     atomicMax(&st->samp_maxe, L.maxe);
   }
-  if (!last_block(j.done + D_SAMPLE * 8 + comp, &L.last, nvb)) return;
+  if (!tail || !last_block(j.done + D_SAMPLE * 8 + comp, &L.last, nvb)) return;
   if (tid < 64) select_sample_body(j, comp);
 }
 
 template <int N, int PREC>
 __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_sample(Job j) {
   __shared__ SampleLds<N, PREC> L;
-  sample_body<N, PREC>(j, blockIdx.y, blockIdx.x, gridDim.x, L);
+  sample_body<N, PREC>(j, blockIdx.y, blockIdx.x, gridDim.x, L, false);
 }
 
 // ---- pass A -------------------------------------------------------------------
@@ -674,7 +601,7 @@ struct PassBLds {
 };
 
 template <int N, int PREC>
-DEV void passB_body(const Job& j, int comp, int vb, int nvb, PassBLds<N, PREC>& L) {
+DEV void passB_body(const Job& j, int comp, int vb, int nvb, PassBLds<N, PREC>& L, bool tail) {
   typedef Eng<N, PREC> G;
   constexpr int n3 = G::n3, NS = G::NS, EPW = G::EPW, W = G::W;
   constexpr bool EXACT = PREC == P_FP64;
@@ -858,20 +785,14 @@ DEV void passB_body(const Job& j, int comp, int vb, int nvb, PassBLds<N, PREC>& 
   xints(ar, PR, v);
   block_sum_i64<3>(v, L.red, tid);
   if (tid < 3) j.slotsB[((size_t)comp * j.gB + vb) * 4 + tid] = L.red[0][tid];
-  if (!last_block(j.done + D_PASSB * 8 + comp, &L.last, nvb)) return;
-  // the component's error total, then its final statistics
-  __int128 K[3];
-  block_totals<3>(j.slotsB + (size_t)comp * j.gB * 4, j.gB, 4, K, L.r3, tid);
-  if (tid == 0) emit_total(gR, K, PR.m, PR.h, -1);
-  __threadfence();
-  __syncthreads();
-  if (tid < 64) finalize_body(j, comp);
+  if (!tail || !last_block(j.done + D_PASSB * 8 + comp, &L.last, nvb)) return;
+  passB_tail(j, comp, L.r3);
 }
 
 template <int N, int PREC>
 __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passB(Job j) {
   __shared__ PassBLds<N, PREC> L;
-  passB_body<N, PREC>(j, blockIdx.y, blockIdx.x, gridDim.x, L);
+  passB_body<N, PREC>(j, blockIdx.y, blockIdx.x, gridDim.x, L, false);
 }
 
 // ---- launchers ------------------------------------------------------------------

@@ -203,7 +203,7 @@ struct SampleLdsD {
 };
 
 template <int N, int PREC, int T>
-DEV void sampleD_body(const Job& j, int comp, int vb, int nvb, SampleLdsD<N, PREC, T>& L) {
+DEV void sampleD_body(const Job& j, int comp, int vb, int nvb, SampleLdsD<N, PREC, T>& L, bool tail) {
   typedef EngD<N, PREC, T> G;
   constexpr int n3 = G::n3, S = G::S;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -281,14 +281,14 @@ DEV void sampleD_body(const Job& j, int comp, int vb, int nvb, SampleLdsD<N, PRE
     atomicAdd(&st->samp_u2, L.u2[0] + L.u2[1] + L.u2[2] + L.u2[3]);
     atomicMax(&st->samp_maxe, L.maxe);
   }
-  if (!last_block(j.done + D_SAMPLE * 8 + comp, &L.last, nvb)) return;
+  if (!tail || !last_block(j.done + D_SAMPLE * 8 + comp, &L.last, nvb)) return;
   if (tid < 64) select_sample_body(j, comp);
 }
 
 template <int N, int PREC, int T>
 __global__ __launch_bounds__(256, ISR_DENSE_MINB) void k_sampleD(Job j) {
   __shared__ SampleLdsD<N, PREC, T> L;
-  sampleD_body<N, PREC, T>(j, blockIdx.y, blockIdx.x, gridDim.x, L);
+  sampleD_body<N, PREC, T>(j, blockIdx.y, blockIdx.x, gridDim.x, L, false);
 }
 
 // ---- pass A ---------------------------------------------------------------------
@@ -442,7 +442,7 @@ struct PassBLdsD {
 };
 
 template <int N, int PREC, int T>
-DEV void passBD_body(const Job& j, int comp, int vb, int nvb, PassBLdsD<N, PREC, T>& L) {
+DEV void passBD_body(const Job& j, int comp, int vb, int nvb, PassBLdsD<N, PREC, T>& L, bool tail) {
   typedef EngD<N, PREC, T> G;
   constexpr int n3 = G::n3, S = G::S, W = G::W;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -564,19 +564,14 @@ DEV void passBD_body(const Job& j, int comp, int vb, int nvb, PassBLdsD<N, PREC,
   xints(ar, PR, v);
   block_sum_i64<3>(v, L.red, tid);
   if (tid < 3) j.slotsB[((size_t)comp * j.gB + vb) * 4 + tid] = L.red[0][tid];
-  if (!last_block(j.done + D_PASSB * 8 + comp, &L.last, nvb)) return;
-  __int128 K[3];
-  block_totals<3>(j.slotsB + (size_t)comp * j.gB * 4, j.gB, 4, K, L.r3, tid);
-  if (tid == 0) emit_total(gR, K, PR.m, PR.h, -1);
-  __threadfence();
-  __syncthreads();
-  if (tid < 64) finalize_body(j, comp);
+  if (!tail || !last_block(j.done + D_PASSB * 8 + comp, &L.last, nvb)) return;
+  passB_tail(j, comp, L.r3);
 }
 
 template <int N, int PREC, int T>
 __global__ __launch_bounds__(256, dense_minb_b<N>()) void k_passBD(Job j) {
   __shared__ PassBLdsD<N, PREC, T> L;
-  passBD_body<N, PREC, T>(j, blockIdx.y, blockIdx.x, gridDim.x, L);
+  passBD_body<N, PREC, T>(j, blockIdx.y, blockIdx.x, gridDim.x, L, false);
 }
 
 // ---- launchers ------------------------------------------------------------------

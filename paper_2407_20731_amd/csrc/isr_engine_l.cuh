@@ -145,7 +145,6 @@ struct SampleLdsL {
   float hs[SBINS];  // sums of energy / 2^(bin exponent), each term in [1, 2)
   double u2[4];
   int maxe;
-  int last;
 };
 
 // Forward transform of element e (field tile at `tile`) into buf; the norm
@@ -244,8 +243,6 @@ __global__ __launch_bounds__(256, 2) void k_sampleL(Job j) {
     atomicAdd(&st->samp_u2, L.u2[0] + L.u2[1] + L.u2[2] + L.u2[3]);
     atomicMax(&st->samp_maxe, L.maxe);
   }
-  if (!last_block(j.done + D_SAMPLE * 8 + comp, &L.last, gridDim.x)) return;
-  if (tid < 64) select_sample_body(j, comp);
 }
 
 template <int N, int PREC>
@@ -358,8 +355,6 @@ struct PassBLdsL {
   u32 wp[4][EngL<N, PREC>::W];
   TabLdsL<EngL<N, PREC>::n3> tab;
   long long red[4][8];
-  __int128 r3[4][3];
-  int last;
 };
 
 template <int N, int PREC>
@@ -497,13 +492,6 @@ __global__ __launch_bounds__(256, 2) void k_passBL(Job j) {
   xints(ar, PR, v);
   block_sum_i64<3>(v, L.red, tid);
   if (tid < 3) j.slotsB[((size_t)comp * j.gB + blockIdx.x) * 4 + tid] = L.red[0][tid];
-  if (!last_block(j.done + D_PASSB * 8 + comp, &L.last, gridDim.x)) return;
-  __int128 K[3];
-  block_totals<3>(j.slotsB + (size_t)comp * j.gB * 4, j.gB, 4, K, L.r3, tid);
-  if (tid == 0) emit_total(gR, K, PR.m, PR.h, -1);
-  __threadfence();
-  __syncthreads();
-  if (tid < 64) finalize_body(j, comp);
 }
 
 #define ISR_FAST_ORDERS_L(X) X(8) X(9) X(10) X(11)

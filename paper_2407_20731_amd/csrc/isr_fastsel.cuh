@@ -3,12 +3,95 @@
 // (isr_fbatch.cuh) run the same code.  A body takes the component, the index
 // of its (virtual) workgroup and their count in place of blockIdx / gridDim;
 // every thread of the workgroup calls it.
+//
+// A phase whose result needs every workgroup's share (a selection, a total)
+// ends in a tail that runs once per component.  The per-phase launches run
+// the tail as a kernel of its own after the phase (the kernel boundary makes
+// the shares visible); the persistent batch, which has no such boundary, runs
+// it in the last workgroup to finish (`tail` = true), behind a device-scope
+// fence in every workgroup.  The fence writes back the L2 cache of the
+// workgroup's XCD, which costs tens of microseconds over a few hundred
+// workgroups, so the per-phase launches avoid it.
 #pragma once
 
 #include "isr_selbody.cuh"
 #include "isr_xsum.cuh"
 
 namespace isr {
+
+// One wave per component: window [b - 1, b + 2) around the bin b where the
+// rounded cumulative sampled energy first exceeds tol^2 * (sampled U2), and
+// the norm-term bound 2^(largest sampled exponent + 8).
+DEV void select_sample_body(const Job& j, int comp) {
+  const int lane = lane_id();
+  CompState* st = j.st + comp;
+  const HistBin* H = j.histEs + (size_t)comp * HBINS;
+  if (lane == 0) {
+    const int mx = st->samp_maxe;  // biased; 0 when every sampled term is 0
+    int m = mx - 1023 + 8;
+    m = m < XM_MIN ? XM_MIN : (m > XM_MAX ? XM_MAX : m);
+    st->xm_norm = m;
+    st->win_mode = 1;
+  }
+  const double tol = j.tol;
+  if (tol < 0.0) {  // keep everything: no window, every energy counts as "above"
+    if (lane == 0) st->win_lo = st->win_hi = 0;
+    return;
+  }
+  const double B = (tol * tol) * st->samp_u2;
+  double cs = 0.0;
+  u64 cc = 0;
+  for (int k = 0; k < 32; ++k) {
+    const int b = 32 * lane + k;
+    if (b < HBINS - 1) {
+      cs += __longlong_as_double((long long)H[b].lo);
+      cc += H[b].cnt;
+    }
+  }
+  double incl = cs;
+  for (int d = 1; d < 64; d <<= 1) {
+    const double o = __shfl_up(incl, d);
+    if (lane >= d) incl += o;
+  }
+  const u64 over = ballot(incl > B);
+  const u64 nonempty = ballot(cc != 0ull);
+  int bstar = -1;
+  if (over) {
+    const int fl = __ffsll((long long)over) - 1;
+    double cum = __shfl(incl - cs, fl);
+    for (int k = 0; k < 32; ++k) {
+      const int b = 32 * fl + k;
+      if (b >= HBINS - 1) break;
+      cum += __longlong_as_double((long long)H[b].lo);
+      if (cum > B) {
+        bstar = b;
+        break;
+      }
+    }
+  } else if (nonempty) {
+    // every sampled energy fits the budget: the top bin (tau is likely +inf,
+    // which the general pipeline handles)
+    const int fl = 63 - __clzll((long long)nonempty);
+    for (int k = 31; k >= 0; --k) {
+      const int b = 32 * fl + k;
+      if (b < HBINS - 1 && H[b].cnt) {
+        bstar = b;
+        break;
+      }
+    }
+  }
+  if (lane == 0) {
+    const int wl = bstar - 1 < 1 ? 1 : bstar - 1;
+    const int wh = bstar + 2 > HBINS - 2 ? HBINS - 2 : bstar + 2;
+    if (bstar < 0 || wl - 1023 < XM_MIN || wl >= wh) {
+      st->flags |= ST_MISS;
+      st->resolved = 1;
+    } else {
+      st->win_lo = wl;
+      st->win_hi = wh;
+    }
+  }
+}
 
 // refine level L over the candidate lists, then (last workgroup of the
 // component) the level-L selection
@@ -29,71 +112,34 @@ DEV void refsel_body(const Job& j, int comp, int L, int vb, int nvb, RefselLds& 
 
 // ---- streaming path: exact window bins, exact totals, level-1 selection ------
 // Every workgroup adds the significands of its share of list 0 (the window
-// energies) to the window bins; workgroup 0 turns the per-workgroup integer
-// sums of pass A into exact bins (norm terms anywhere, energies below the
-// window in bins below it) and puts the count of energies above the window
-// into bin win_hi; the last workgroup runs the level-1 selection.
+// energies) to the window bins (integer sums: exact in any order).  The tail
+// turns the per-workgroup integer sums of pass A into exact bins (norm terms
+// anywhere, energies below the window in bins below it), puts the count of
+// energies above the window into bin win_hi and runs the level-1 selection.
 struct GatherLds {
   u64 red[4][9];
-  __int128 r7[4][7], r9[4][9];
+  __int128 r7[4][7];
   int last;
 };
 
-DEV void gather_body(const Job& j, int comp, int vb, int nvb, GatherLds& X) {
-  u64(&red)[4][9] = X.red;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+DEV void gather_tail(const Job& j, int comp, GatherLds& X) {
+  const int tid = threadIdx.x;
   CompState* st = j.st + comp;
   if (st->flags & ST_MISS) return;
   const int wlo = st->win_lo, whi = st->win_hi;
   HistBin* gE = j.histE + (size_t)comp * HBINS;
   HistBin* gN = j.histN + (size_t)comp * HBINS;
-  const u64* list = list_ptr(j, comp, 0);
-  const u64 nl = st->list_count[0] < j.list_cap ? st->list_count[0] : j.list_cap;
-  u64 acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // (cnt, lo, hi) of the three window bins
-  for (u64 i = (u64)vb * 256 + tid; i < nl; i += (u64)nvb * 256) {
-    const u64 key = list[i];
-    const int k = (int)(key >> 52) - wlo;  // 0..2; window bins are >= 1 (normal numbers)
-    const u64 sig = (key & M52) | (1ull << 52);
-    for (int b = 0; b < 3; ++b) {
-      if (b == k) {
-        acc[3 * b] += 1ull;
-        acc[3 * b + 1] += sig & M21;
-        acc[3 * b + 2] += sig >> 21;
-      }
-    }
-  }
-  for (int k = 0; k < 9; ++k) {
-    const u64 w = wave_sum64(acc[k]);
-    if (lane == 0) red[wv][k] = w;
-  }
-  __syncthreads();
-  // per-workgroup partials (no contended atomics); the last workgroup adds them
-  if (tid < 9) j.gslot[((size_t)comp * GATHER_GMAX + vb) * 16 + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-  if (vb == 0) {
-    // totals of pass A's workgroup sums: fields 0..2 norm, 3..5 energy, 6 count
-    __int128 T[7];
-    block_totals<7>(j.slotsA + (size_t)comp * j.gA * 8, j.gA, 8, T, X.r7, tid);
-    if (tid == 0) {
-      __int128 K[3];
-      for (int k = 0; k < 3; ++k) K[k] = T[k];
-      emit_total(gN, K, st->xm_norm, j.xh, -1);
-      for (int k = 0; k < 3; ++k) K[k] = T[3 + k];
-      if (wlo < whi) emit_total(gE, K, wlo - 1023, j.xh, wlo - 1);
-      const u64 above = (u64)T[6];
-      if (above) atomicAdd(&gE[whi].cnt, above);
-    }
-  }
-  if (!last_block(j.done + D_GATHER * 8 + comp, &X.last, nvb)) return;
-  __int128 T9[9];
-  block_totals<9>((const long long*)j.gslot + (size_t)comp * GATHER_GMAX * 16, nvb, 16, T9, X.r9, tid);
-  for (int k = 0; k < 9; ++k) {
-    const u64 w = (u64)T9[k];
-    const int b = wlo + k / 3;
-    if (tid == 0 && w && b < whi) {
-      if (k % 3 == 0) atomicAdd(&gE[b].cnt, w);
-      if (k % 3 == 1) atomicAdd(&gE[b].lo, w);
-      if (k % 3 == 2) atomicAdd(&gE[b].hi, w);
-    }
+  // totals of pass A's workgroup sums: fields 0..2 norm, 3..5 energy, 6 count
+  __int128 T[7];
+  block_totals<7>(j.slotsA + (size_t)comp * j.gA * 8, j.gA, 8, T, X.r7, tid);
+  if (tid == 0) {
+    __int128 K[3];
+    for (int k = 0; k < 3; ++k) K[k] = T[k];
+    emit_total(gN, K, st->xm_norm, j.xh, -1);
+    for (int k = 0; k < 3; ++k) K[k] = T[3 + k];
+    if (wlo < whi) emit_total(gE, K, wlo - 1023, j.xh, wlo - 1);
+    const u64 above = (u64)T[6];
+    if (above) atomicAdd(&gE[whi].cnt, above);
   }
   __threadfence();
   __syncthreads();
@@ -113,10 +159,62 @@ DEV void gather_body(const Job& j, int comp, int vb, int nvb, GatherLds& X) {
   }
 }
 
+DEV void gather_body(const Job& j, int comp, int vb, int nvb, GatherLds& X, bool tail) {
+  u64(&red)[4][9] = X.red;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  CompState* st = j.st + comp;
+  if (st->flags & ST_MISS) return;
+  const int wlo = st->win_lo, whi = st->win_hi;
+  HistBin* gE = j.histE + (size_t)comp * HBINS;
+  const u64* list = list_ptr(j, comp, 0);
+  const u64 nl = st->list_count[0] < j.list_cap ? st->list_count[0] : j.list_cap;
+  u64 acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // (cnt, lo, hi) of the three window bins
+  // four entries per lane per step, loaded before any is used
+  constexpr int U = 4;
+  const u64 stride = (u64)nvb * 256;
+  for (u64 i0 = (u64)vb * 256 + tid; i0 < nl; i0 += U * stride) {
+    u64 keys[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const u64 i = i0 + u * stride;
+      keys[u] = i < nl ? list[i] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (i0 + u * stride >= nl) continue;
+      const u64 key = keys[u];
+      const int k = (int)(key >> 52) - wlo;  // 0..2; window bins are >= 1 (normal numbers)
+      const u64 sig = (key & M52) | (1ull << 52);
+      for (int b = 0; b < 3; ++b) {
+        if (b == k) {
+          acc[3 * b] += 1ull;
+          acc[3 * b + 1] += sig & M21;
+          acc[3 * b + 2] += sig >> 21;
+        }
+      }
+    }
+  }
+  for (int k = 0; k < 9; ++k) {
+    const u64 w = wave_sum64(acc[k]);
+    if (lane == 0) red[wv][k] = w;
+  }
+  __syncthreads();
+  if (tid < 9) {
+    const u64 w = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    const int b = wlo + tid / 3;
+    if (w && b < whi) {
+      HistBin& h = gE[b];
+      atomicAdd(tid % 3 == 0 ? &h.cnt : (tid % 3 == 1 ? &h.lo : &h.hi), w);
+    }
+  }
+  if (!tail || !last_block(j.done + D_GATHER * 8 + comp, &X.last, nvb)) return;
+  gather_tail(j, comp, X);
+}
+
 // Per-element kept counts: pass A stored the count of energies above the
 // window; every window entry of list 0 at or above tau adds one.
 DEV void count_body(const Job& j, int comp, int vb, int nvb) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   CompState* st = j.st + comp;
   if (st->flags & ST_MISS) return;
   u32* cnt = j.cnt + (size_t)comp * j.n_elem;
@@ -124,8 +222,36 @@ DEV void count_body(const Job& j, int comp, int vb, int nvb) {
   const u64* list = list_ptr(j, comp, 0);
   const u32* lidx = j.lidx + (size_t)comp * j.list_cap;
   const u64 nl = st->list_count[0] < j.list_cap ? st->list_count[0] : j.list_cap;
-  for (u64 i = (u64)vb * 256 + tid; i < nl; i += (u64)nvb * 256)
-    if (list[i] >= tk) atomicAdd(&cnt[lidx[i]], 1u);
+  constexpr int U = 4;
+  const u64 stride = (u64)nvb * 256;
+  // the trip count is the same for every lane of a wave (ballots inside)
+  const u64 nl_r = (nl + 63) & ~63ull;
+  for (u64 i0 = (u64)vb * 256 + tid; i0 < nl_r; i0 += U * stride) {
+    u64 keys[U];
+    u32 idx[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const u64 i = i0 + u * stride;
+      keys[u] = i < nl ? list[i] : 0ull;
+      idx[u] = i < nl ? lidx[i] : 0u;
+    }
+    // list entries of one element sit close together: one atomic per
+    // distinct element of the wave (leader = lowest lane) instead of one per
+    // entry
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      bool act = i0 + u * stride < nl && keys[u] >= tk;
+      u64 m = ballot(act);
+      while (m) {
+        const int l = __ffsll((long long)m) - 1;
+        const u32 el = (u32)__shfl((int)idx[u], l);
+        const u64 same = ballot(act && idx[u] == el);
+        if (lane == l) atomicAdd(&cnt[el], (u32)__popcll(same));
+        act = act && idx[u] != el;
+        m &= ~same;
+      }
+    }
+  }
 }
 
 // Element offsets from the counts, in two steps over chunks of SCAN_CHUNK
@@ -152,7 +278,31 @@ struct ScanLds {
   int last;
 };
 
-DEV void scan1_body(const Job& j, int comp, int vb, int nvb, ScanLds& X) {
+DEV void scan1_tail(const Job& j, int comp, ScanLds& X) {
+  u64* part = X.part;
+  const int tid = threadIdx.x;
+  CompState* st = j.st + comp;
+  if (st->flags & ST_MISS) return;
+  const long long E = j.n_elem;
+  const long long nch = (E + SCAN_CHUNK - 1) / SCAN_CHUNK;
+  u64* coff = j.chunk + (size_t)comp * j.nchunk;
+  // chunk sums -> exclusive chunk offsets (in place), total check
+  u64 run = 0;
+  for (long long c0 = 0; c0 < nch; c0 += 256) {
+    const long long c = c0 + tid;
+    const u64 v = c < nch ? coff[c] : 0ull;
+    u64 tot;
+    const u64 ex = block_excl_scan(v, part, tid, &tot);
+    if (c < nch) coff[c] = run + ex;
+    run += tot;
+  }
+  if (tid == 0) {
+    j.elem_ptr[(size_t)comp * (E + 1) + E] = run;
+    if (run != st->kept) atomicOr(&st->flags, ST_LIST);
+  }
+}
+
+DEV void scan1_body(const Job& j, int comp, int vb, int nvb, ScanLds& X, bool tail) {
   u64* part = X.part;
   const int tid = threadIdx.x;
   CompState* st = j.st + comp;
@@ -171,21 +321,8 @@ DEV void scan1_body(const Job& j, int comp, int vb, int nvb, ScanLds& X) {
     (void)block_excl_scan(v, part, tid, &tot);
     if (tid == 0) coff[c] = tot;
   }
-  if (!last_block(j.done + D_COUNT * 8 + comp, &X.last, nvb)) return;
-  // chunk sums -> exclusive chunk offsets (in place), total check
-  u64 run = 0;
-  for (long long c0 = 0; c0 < nch; c0 += 256) {
-    const long long c = c0 + tid;
-    const u64 v = c < nch ? coff[c] : 0ull;
-    u64 tot;
-    const u64 ex = block_excl_scan(v, part, tid, &tot);
-    if (c < nch) coff[c] = run + ex;
-    run += tot;
-  }
-  if (tid == 0) {
-    j.elem_ptr[(size_t)comp * (E + 1) + E] = run;
-    if (run != st->kept) atomicOr(&st->flags, ST_LIST);
-  }
+  if (!tail || !last_block(j.done + D_COUNT * 8 + comp, &X.last, nvb)) return;
+  scan1_tail(j, comp, X);
 }
 
 DEV void scan2_body(const Job& j, int comp, int vb, int nvb, ScanLds& X) {
@@ -216,5 +353,19 @@ DEV void scan2_body(const Job& j, int comp, int vb, int nvb, ScanLds& X) {
   }
 }
 
+// Pass B's tail: the component's error total from the per-workgroup integer
+// sums, then its final statistics.
+DEV void passB_tail(const Job& j, int comp, __int128 (*r3)[3]) {
+  const int tid = threadIdx.x;
+  CompState* st = j.st + comp;
+  if (st->flags & ST_MISS) return;
+  const XParm PR = xparm(st->xm_err, j.xh);
+  __int128 K[3];
+  block_totals<3>(j.slotsB + (size_t)comp * j.gB * 4, j.gB, 4, K, r3, tid);
+  if (tid == 0) emit_total(j.histR + (size_t)comp * HBINS, K, PR.m, PR.h, -1);
+  __threadfence();
+  __syncthreads();
+  if (tid < 64) finalize_body(j, comp);
+}
 
 }  // namespace isr

@@ -64,7 +64,6 @@ DEV Job fb_job(const Job* jr) {
   j.slotsB = fb_global(j.slotsB);
   j.done = fb_global(j.done);
   j.chunk = fb_global(j.chunk);
-  j.gslot = fb_global(j.gslot);
   j.lookback = fb_global(j.lookback);
   j.ticket = fb_global(j.ticket);
   j.bitmap = fb_global(j.bitmap);
@@ -81,18 +80,18 @@ struct FbOrder {
   typedef SampleLdsD<N, PREC, T> LS;
   typedef PassALdsD<N, PREC, T> LA;
   typedef PassBLdsD<N, PREC, T> LB;
-  static DEV void sample(const Job& j, int c, int k, int nk) { sampleD_body<N, PREC, T>(j, c, k, nk, *(LS*)fb_lds); }
+  static DEV void sample(const Job& j, int c, int k, int nk) { sampleD_body<N, PREC, T>(j, c, k, nk, *(LS*)fb_lds, true); }
   static DEV void passA(const Job& j, int c, int k, int nk) { passAD_body<N, PREC, T>(j, c, k, nk, *(LA*)fb_lds); }
-  static DEV void passB(const Job& j, int c, int k, int nk) { passBD_body<N, PREC, T>(j, c, k, nk, *(LB*)fb_lds); }
+  static DEV void passB(const Job& j, int c, int k, int nk) { passBD_body<N, PREC, T>(j, c, k, nk, *(LB*)fb_lds, true); }
 };
 template <int N, int PREC>
 struct FbOrder<N, PREC, 0> {
   typedef SampleLds<N, PREC> LS;
   typedef PassALds<N, PREC> LA;
   typedef PassBLds<N, PREC> LB;
-  static DEV void sample(const Job& j, int c, int k, int nk) { sample_body<N, PREC>(j, c, k, nk, *(LS*)fb_lds); }
+  static DEV void sample(const Job& j, int c, int k, int nk) { sample_body<N, PREC>(j, c, k, nk, *(LS*)fb_lds, true); }
   static DEV void passA(const Job& j, int c, int k, int nk) { passA_body<N, PREC>(j, c, k, nk, *(LA*)fb_lds); }
-  static DEV void passB(const Job& j, int c, int k, int nk) { passB_body<N, PREC>(j, c, k, nk, *(LB*)fb_lds); }
+  static DEV void passB(const Job& j, int c, int k, int nk) { passB_body<N, PREC>(j, c, k, nk, *(LB*)fb_lds, true); }
 };
 
 template <int PREC>
@@ -121,7 +120,7 @@ __device__ __noinline__ void fb_passB(const Job* jr, int comp, int k, int nk) {
 }
 __device__ __noinline__ void fb_gather(const Job* jr, int comp, int k, int nk) {
   const Job j = fb_job(jr);
-  gather_body(j, fb_u(comp), fb_u(k), fb_u(nk), *reinterpret_cast<GatherLds*>(fb_lds));
+  gather_body(j, fb_u(comp), fb_u(k), fb_u(nk), *reinterpret_cast<GatherLds*>(fb_lds), true);
 }
 __device__ __noinline__ void fb_refsel(const Job* jr, int comp, int L, int k, int nk) {
   const Job j = fb_job(jr);
@@ -133,7 +132,7 @@ __device__ __noinline__ void fb_count(const Job* jr, int comp, int k, int nk) {
 }
 __device__ __noinline__ void fb_scan1(const Job* jr, int comp, int k, int nk) {
   const Job j = fb_job(jr);
-  scan1_body(j, fb_u(comp), fb_u(k), fb_u(nk), *reinterpret_cast<ScanLds*>(fb_lds));
+  scan1_body(j, fb_u(comp), fb_u(k), fb_u(nk), *reinterpret_cast<ScanLds*>(fb_lds), true);
 }
 __device__ __noinline__ void fb_scan2(const Job* jr, int comp, int k, int nk) {
   const Job j = fb_job(jr);

@@ -120,7 +120,6 @@ struct Job {
   long long* slotsB;   // [ncomp][gB][4]
   u32* done;           // [16][8] finished-workgroup counters
   u64* chunk;          // [ncomp][nchunk] element-offset scan: chunk sums, then offsets
-  u64* gslot;          // [ncomp][GATHER_GMAX][16] per-workgroup window-bin partials
   long long nchunk;
   int gA, gB;          // workgroups per component of the two streaming passes
   int xh;              // extraction headroom (log2 of twice the terms per lane)
@@ -240,6 +239,9 @@ inline long long fast_lane_terms(int order, int tile) {
 constexpr int FAST_GMAX = 2048;  // workgroups per component of a streaming pass
 constexpr int GATHER_GMAX = 256;  // workgroups per component of the window-bin gather
 hipError_t launch_fast(int kind, int precision, const Job& j, int grid_x, hipStream_t s);
+// per-component tail of the sample pass (window selection) or of pass B
+// (error total and final statistics), after that pass
+hipError_t launch_fast_tail(int kind, const Job& j, hipStream_t s);
 int resident_fast(int kind, int precision, int order, int tile);
 hipError_t launch_dense_fp32(int kind, const Job& j, int grid_x, hipStream_t s);
 hipError_t launch_dense_bf16(int kind, const Job& j, int grid_x, hipStream_t s);

@@ -339,7 +339,6 @@ Sizes plan_sizes(const isr_field* f, int tile) {
     z.off_slotsA = take((size_t)nc * FAST_GMAX * 8 * 8);
     z.off_slotsB = take((size_t)nc * FAST_GMAX * 4 * 8);
     z.off_chunk = take((size_t)nc * ((f->n_elem + 1023) / 1024) * 8);
-    z.off_gslot = take((size_t)nc * GATHER_GMAX * 16 * 8);
   }
   z.scratch_bytes = o;
   z.blob_max = 256 + (size_t)nc * f->n_elem * z.W * 8 + (size_t)nc * (f->n_elem + 1) * 8 + (size_t)nc * z.nv * z.vbytes;
@@ -383,7 +382,6 @@ static Job make_job(isr_ctx* c, const isr_field* f, const Sizes& z, char* scratc
     j.slotsA = (long long*)(scratch + z.off_slotsA);
     j.slotsB = (long long*)(scratch + z.off_slotsB);
     j.chunk = (u64*)(scratch + z.off_chunk);
-    j.gslot = (u64*)(scratch + z.off_gslot);
     j.nchunk = (f->n_elem + 1023) / 1024;
   }
   j.bitmap = b->bitmap();
@@ -450,9 +448,11 @@ static int enqueue_fast(isr_ctx* c, const Job& j0, const Sizes& z, hipStream_t s
   auto rec = [&](int k) {
     if (ev) (void)hipEventRecord(ev[k], s);
   };
+  rec(7);
   HIPCHK(launch_zero((void*)j.histE, z.zero_bytes, s));
-  rec(0);
   HIPCHK(launch_fast(F_SAMPLE, prec, j, g.gs, s));
+  HIPCHK(launch_fast_tail(F_SAMPLE, j, s));
+  rec(0);
   HIPCHK(launch_fast(F_PASSA, prec, j, j.gA, s));
   rec(1);
   HIPCHK(launch_gather(j, g.gl, s));
@@ -463,6 +463,7 @@ static int enqueue_fast(isr_ctx* c, const Job& j0, const Sizes& z, hipStream_t s
   rec(4);
   HIPCHK(launch_fast(F_PASSB, prec, j, j.gB, s));
   rec(5);
+  HIPCHK(launch_fast_tail(F_PASSB, j, s));
   rec(6);
   return ISR_OK;
 }
@@ -484,8 +485,8 @@ int enqueue_pipeline(isr_ctx* c, const Job& j, const Sizes& z, hipStream_t s, hi
   auto rec = [&](int k) {
     if (ev) (void)hipEventRecord(ev[k], s);
   };
+  rec(7);
   HIPCHK(launch_zero((void*)j.histE, z.zero_bytes, s));
-  rec(0);
   if (j.sample_stride > 0) {
     const long long stiles = (tiles + j.sample_stride - 1) / j.sample_stride;
     const long long slots = (long long)c->num_cu * resident_blocks(K_PASS1, prec, j.order);
@@ -493,6 +494,7 @@ int enqueue_pipeline(isr_ctx* c, const Job& j, const Sizes& z, hipStream_t s, hi
     HIPCHK(launch_pass(K_PASS1, prec, j, sgx, s, nullptr, 1));
     HIPCHK(launch_select1(j, 1, s));
   }
+  rec(0);
   HIPCHK(launch_pass(K_PASS1, prec, j, grid_per_comp(K_PASS1), s, nullptr, 0));
   rec(1);
   HIPCHK(launch_select1(j, 0, s));
@@ -685,7 +687,7 @@ int task_step(Task* t, isr_blob** out) {
     // (no sample window this time), keeping any budget override
     if (t->timing) {
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, t->ev[0], t->ev[6]) == hipSuccess) t->st.phase_ms[7] += ms;
+      if (hipEventElapsedTime(&ms, t->ev[7], t->ev[6]) == hipSuccess) t->st.phase_ms[7] += ms;
     }
     t->fast = false;
     t->j.sample_stride = 0;
@@ -702,9 +704,12 @@ int task_step(Task* t, isr_blob** out) {
     return rc;
   }
   if (t->timing) {
-    float ms[6];
+    // phases 0..5 between events 0..6; phase 8 (zero fill, sample pass and
+    // window selection) from event 7 to event 0
+    float ms[9] = {};
     for (int k = 0; k < 6; ++k) (void)hipEventElapsedTime(&ms[k], t->ev[k], t->ev[k + 1]);
-    for (int k = 0; k < 6; ++k) {
+    (void)hipEventElapsedTime(&ms[8], t->ev[7], t->ev[0]);
+    for (int k : {0, 1, 2, 3, 4, 5, 8}) {
       if (t->iters == 0)
         t->st.phase_ms[k] = ms[k];
       else

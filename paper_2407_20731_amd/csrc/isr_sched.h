@@ -56,7 +56,7 @@ struct Sizes {
   int vbytes = 8;
   size_t off_histE = 0, off_histN = 0, off_histR = 0, off_histL = 0, off_st = 0, off_ticket = 0,
          off_lookback = 0, off_lists = 0, off_histEs = 0, off_histNs = 0, off_done = 0, off_lidx = 0, off_cnt = 0,
-         off_slotsA = 0, off_slotsB = 0, off_chunk = 0, off_gslot = 0;
+         off_slotsA = 0, off_slotsB = 0, off_chunk = 0;
   bool fast = false;         // streaming path
   int tile = 0;              // its dense-tile shape (elements per wavefront tile); 0 = wave-tile engine
   int gA = 0, gB = 0, xh = 0;  // its grids (workgroups per component) and extraction headroom
@@ -89,7 +89,7 @@ struct Task {
   hipStream_t s = nullptr;
   CompState* hs = nullptr;   // pinned copy of the per-component state
   hipEvent_t done = nullptr; // recorded after the state copy
-  hipEvent_t ev[7] = {};
+  hipEvent_t ev[8] = {};
   bool timing = false;
   bool fast = false;         // this attempt runs the streaming path
   int iters = 0;

@@ -39,21 +39,35 @@ __global__ __launch_bounds__(64) void k_finalize(Job j) { finalize_body(j, block
 
 // Per-phase launches of the streaming path's order-independent bodies
 // (isr_fastsel.cuh).
-__global__ __launch_bounds__(256) void k_refsel(Job j, int L) {
-  __shared__ RefselLds X;
-  refsel_body(j, blockIdx.y, L, blockIdx.x, gridDim.x, X);
-}
-
 __global__ __launch_bounds__(256) void k_gather(Job j) {
   __shared__ GatherLds X;
-  gather_body(j, blockIdx.y, blockIdx.x, gridDim.x, X);
+  gather_body(j, blockIdx.y, blockIdx.x, gridDim.x, X, false);
 }
 
 __global__ __launch_bounds__(256) void k_count(Job j) { count_body(j, blockIdx.y, blockIdx.x, gridDim.x); }
 
 __global__ __launch_bounds__(256) void k_scan1(Job j) {
   __shared__ ScanLds X;
-  scan1_body(j, blockIdx.y, blockIdx.x, gridDim.x, X);
+  scan1_body(j, blockIdx.y, blockIdx.x, gridDim.x, X, false);
+}
+
+// Per-component tails of the phases above and of the sample pass and pass B
+// (one workgroup per component, after the phase's kernel).
+__global__ __launch_bounds__(256) void k_gather_tail(Job j) {
+  __shared__ GatherLds X;
+  gather_tail(j, blockIdx.x, X);
+}
+
+__global__ __launch_bounds__(256) void k_scan1_tail(Job j) {
+  __shared__ ScanLds X;
+  scan1_tail(j, blockIdx.x, X);
+}
+
+__global__ __launch_bounds__(64) void k_sample_tail(Job j) { select_sample_body(j, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_passB_tail(Job j) {
+  __shared__ __int128 r3[4][3];
+  passB_tail(j, blockIdx.x, r3);
 }
 
 __global__ __launch_bounds__(256) void k_scan2(Job j) {
@@ -61,14 +75,17 @@ __global__ __launch_bounds__(256) void k_scan2(Job j) {
   scan2_body(j, blockIdx.y, blockIdx.x, gridDim.x, X);
 }
 
+// refinement level L, then its selection as a kernel of its own
 hipError_t launch_refsel(const Job& j, int L, int gx, hipStream_t s) {
-  hipLaunchKernelGGL(k_refsel, dim3(gx, j.ncomp), dim3(256), 0, s, j, L);
+  hipLaunchKernelGGL(k_refine, dim3(gx, j.ncomp), dim3(256), 0, s, j, L);
+  hipLaunchKernelGGL(k_select, dim3(j.ncomp), dim3(256), 0, s, j, L);
   return hipGetLastError();
 }
 
 hipError_t launch_gather(const Job& j, int gx, hipStream_t s) {
   if (gx > GATHER_GMAX) gx = GATHER_GMAX;
   hipLaunchKernelGGL(k_gather, dim3(gx, j.ncomp), dim3(256), 0, s, j);
+  hipLaunchKernelGGL(k_gather_tail, dim3(j.ncomp), dim3(256), 0, s, j);
   return hipGetLastError();
 }
 
@@ -76,6 +93,7 @@ hipError_t launch_count(const Job& j, int gx, hipStream_t s) {
   hipLaunchKernelGGL(k_count, dim3(gx, j.ncomp), dim3(256), 0, s, j);  // independent atomics: many workgroups
   const int g = scan_grid_elems(j.n_elem);
   hipLaunchKernelGGL(k_scan1, dim3(g, j.ncomp), dim3(256), 0, s, j);
+  hipLaunchKernelGGL(k_scan1_tail, dim3(j.ncomp), dim3(256), 0, s, j);
   hipLaunchKernelGGL(k_scan2, dim3(g, j.ncomp), dim3(256), 0, s, j);
   return hipGetLastError();
 }
@@ -113,6 +131,16 @@ int tiles_per_comp(int order, long long n_elem) {
   const int n = order + 1, n2 = n * n;
   const int epi = 256 / n2 > 0 ? 256 / n2 : 1;
   return (int)((n_elem + epi - 1) / epi);
+}
+
+hipError_t launch_fast_tail(int kind, const Job& j, hipStream_t s) {
+  if (kind == F_SAMPLE)
+    hipLaunchKernelGGL(k_sample_tail, dim3(j.ncomp), dim3(64), 0, s, j);
+  else if (kind == F_PASSB)
+    hipLaunchKernelGGL(k_passB_tail, dim3(j.ncomp), dim3(256), 0, s, j);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t launch_fast(int kind, int precision, const Job& j, int gx, hipStream_t s) {

@@ -31,8 +31,8 @@ PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 FLAG_TIMING = 1
 FLAG_BATCH_STREAMS = 2  # FP32/BF16 batches on the scheduler's streams instead of one persistent launch
 MAX_COMP = 8
-NPHASE = 8
-PHASES = ("pass1", "select1", "pass2", "refine", "pass3", "finalize", "repair", "fallback")
+NPHASE = 9
+PHASES = ("pass1", "select1", "pass2", "refine", "pass3", "finalize", "repair", "fallback", "sample")
 PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16": PREC_BF16}
 _STATUS = {OK: "ISR_OK", PENDING: "ISR_PENDING", EINVAL: "ISR_EINVAL", ENOMEM: "ISR_ENOMEM",
            EDEVICE: "ISR_EDEVICE", ETOL: "ISR_ETOL", ECANCELED: "ISR_ECANCELED", ENOTFOUND: "ISR_ENOTFOUND"}
