@@ -184,7 +184,7 @@ hipError_t launch_select1(const Job& j, int sample, hipStream_t s);
 hipError_t launch_refine(const Job& j, int level, int grid_x, hipStream_t s);
 hipError_t launch_select(const Job& j, int level, hipStream_t s);
 hipError_t launch_finalize(const Job& j, hipStream_t s);
-hipError_t launch_refsel(const Job& j, int level, int grid_x, hipStream_t s);
+hipError_t launch_refsel(const Job& j, int grid_x, hipStream_t s);  // levels 2..NLEV
 
 // Streaming path (isr_engine.cuh) for orders 1..7.
 enum FastKind { F_SAMPLE = 0, F_PASSA = 1, F_PASSB = 2 };

@@ -458,7 +458,7 @@ static int enqueue_fast(isr_ctx* c, const Job& j0, const Sizes& z, hipStream_t s
   HIPCHK(launch_gather(j, g.gl, s));
   rec(2);
   rec(3);
-  for (int L = 2; L <= NLEV; ++L) HIPCHK(launch_refsel(j, L, g.rgx, s));
+  HIPCHK(launch_refsel(j, g.rgx, s));
   HIPCHK(launch_count(j, g.gl, s));
   rec(4);
   HIPCHK(launch_fast(F_PASSB, prec, j, j.gB, s));
@@ -502,7 +502,7 @@ int enqueue_pipeline(isr_ctx* c, const Job& j, const Sizes& z, hipStream_t s, hi
   HIPCHK(launch_pass(K_PASS2, prec, j, grid_per_comp(K_PASS2), s));
   rec(3);
   const int rgx = std::max(1, std::min(64, (int)(z.nv >> 20) + 1));
-  for (int L = 2; L <= NLEV; ++L) HIPCHK(launch_refsel(j, L, rgx, s));
+  HIPCHK(launch_refsel(j, rgx, s));
   rec(4);
   const long long slots3 = (long long)c->num_cu * resident_blocks(K_PASS3, prec, j.order);
   const int g3 = (int)std::min<long long>(tiles * nc, slots3);

@@ -75,10 +75,35 @@ __global__ __launch_bounds__(256) void k_scan2(Job j) {
   scan2_body(j, blockIdx.y, blockIdx.x, gridDim.x, X);
 }
 
-// refinement level L, then its selection as a kernel of its own
-hipError_t launch_refsel(const Job& j, int L, int gx, hipStream_t s) {
-  hipLaunchKernelGGL(k_refine, dim3(gx, j.ncomp), dim3(256), 0, s, j, L);
-  hipLaunchKernelGGL(k_select, dim3(j.ncomp), dim3(256), 0, s, j, L);
+// Levels L0..NLEV in one workgroup per component, each refinement followed by
+// its selection.  From level 4 on, the lists hold the members of one level-3
+// sub-bin (a few entries, unless thousands of energies agree in their top 23
+// bits) and the selection has usually been resolved already, so one launch
+// replaces two per level.
+__global__ __launch_bounds__(256) void k_refsel_rest(Job j, int L0) {
+  __shared__ RefselLds X;
+  const int comp = blockIdx.x;
+  for (int L = L0; L <= NLEV; ++L) {
+    if (j.st[comp].resolved) return;
+    refine_body(j, comp, L, X.U.h, 0, 1);
+    __syncthreads();
+    __threadfence();
+    __syncthreads();
+    select_body(j, comp, L, X.U.S);
+    __syncthreads();
+    __threadfence();
+    __syncthreads();
+  }
+}
+
+// the refinement levels 2..NLEV: levels 2 and 3 (over list 0) as a refinement
+// kernel and a selection kernel each, the rest in one launch
+hipError_t launch_refsel(const Job& j, int gx, hipStream_t s) {
+  for (int L = 2; L <= 3; ++L) {
+    hipLaunchKernelGGL(k_refine, dim3(gx, j.ncomp), dim3(256), 0, s, j, L);
+    hipLaunchKernelGGL(k_select, dim3(j.ncomp), dim3(256), 0, s, j, L);
+  }
+  hipLaunchKernelGGL(k_refsel_rest, dim3(j.ncomp), dim3(256), 0, s, j, 4);
   return hipGetLastError();
 }
 
