@@ -149,13 +149,7 @@ struct Eng {
         for (int s = 0; s < 4; ++s) d = __builtin_amdgcn_mfma_f32_16x16x4f32(f[s], (float)x[4 * blk + s], d, 0, 0, 0);
       } else {
         s4 xh, xl;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const float xv = (float)x[4 * blk + v];
-          const short hi = to_bf16(xv);
-          xh[v] = hi;
-          xl[v] = to_bf16(xv - from_bf16(hi));
-        }
+        split_bf16x4((float)x[4 * blk], (float)x[4 * blk + 1], (float)x[4 * blk + 2], (float)x[4 * blk + 3], xh, xl);
         d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(h, xh, d, 0, 0, 0);
         d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(l, xh, d, 0, 0, 0);
         d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(h, xl, d, 0, 0, 0);

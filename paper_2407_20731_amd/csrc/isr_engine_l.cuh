@@ -66,12 +66,7 @@ struct EngL {
       for (int s = 0; s < 4; ++s) d = __builtin_amdgcn_mfma_f32_16x16x4f32(f[s], x[s], d, 0, 0, 0);
     } else {
       s4 xh, xl;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const short hi = to_bf16(x[v]);
-        xh[v] = hi;
-        xl[v] = to_bf16(x[v] - from_bf16(hi));
-      }
+      split_bf16x4(x[0], x[1], x[2], x[3], xh, xl);
       d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(h, xh, d, 0, 0, 0);
       d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(l, xh, d, 0, 0, 0);
       d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(h, xl, d, 0, 0, 0);

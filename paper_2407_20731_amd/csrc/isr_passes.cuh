@@ -144,6 +144,21 @@ struct Xf64 {
 DEV short to_bf16(float x) { return __builtin_bit_cast(short, (__bf16)x); }
 DEV float from_bf16(short h) { return __uint_as_float(((u32)(unsigned short)h) << 16); }
 
+// The same split of four values, hi = RN(x) and lo = RN(x - hi), with two
+// values per conversion instruction (the pairs land packed, as the MFMA
+// operand wants them).
+typedef float fl2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef u32 u32x2 __attribute__((ext_vector_type(2)));
+DEV u32 pk_bf16(float a, float b) { return __builtin_bit_cast(u32, __builtin_convertvector((fl2){a, b}, bf2)); }
+DEV void split_bf16x4(float x0, float x1, float x2, float x3, s4& h, s4& l) {
+  const u32 a = pk_bf16(x0, x1), b = pk_bf16(x2, x3);
+  const u32 c = pk_bf16(x0 - __uint_as_float(a << 16), x1 - __uint_as_float(a & 0xffff0000u));
+  const u32 d = pk_bf16(x2 - __uint_as_float(b << 16), x3 - __uint_as_float(b & 0xffff0000u));
+  h = __builtin_bit_cast(s4, (u32x2){a, b});
+  l = __builtin_bit_cast(s4, (u32x2){c, d});
+}
+
 template <int N, int PREC>
 struct XfM {
   typedef Shape<N> S;
@@ -201,14 +216,13 @@ struct XfM {
         }
       } else {
         s4 xh, xl;
+        float xv[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int k = 4 * (lane / 16) + v;
-          const float x = (valid && k < n) ? (float)src[base + k * si] : 0.0f;
-          const short hi = to_bf16(x);
-          xh[v] = hi;
-          xl[v] = to_bf16(x - from_bf16(hi));
+          xv[v] = (valid && k < n) ? (float)src[base + k * si] : 0.0f;
         }
+        split_bf16x4(xv[0], xv[1], xv[2], xv[3], xh, xl);
         d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xh, fr.h, d, 0, 0, 0);
         d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xh, fr.l, d, 0, 0, 0);
         d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xl, fr.h, d, 0, 0, 0);
