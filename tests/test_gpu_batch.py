@@ -30,6 +30,8 @@ def test_batch_equals_alone(isr_ctx, prec):
     rng = np.random.default_rng(11)
     snaps = _batch(rng, 10, 30, 5000, 700)
     snaps.append((7, 4096, torch.from_numpy(synth.field(4096, 7, seed=799)).cuda()))  # sampled window
+    # 6,000 identical elements: ties beyond the sort cap, every refinement level
+    snaps.append((5, 6000, torch.from_numpy(np.repeat(synth.field(1, 5, seed=5), 6000, axis=1)).cuda()))
     torch.cuda.synchronize()
     print(f"[case] batch prec={prec} sizes={[(N, E) for N, E, _ in snaps]}", flush=True)
     blobs = isr_ctx.compress_batch([(u, N, 1e-3) for N, E, u in snaps], prec)

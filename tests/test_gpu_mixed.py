@@ -124,6 +124,23 @@ def test_mixed_is_deterministic(isr_ctx, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_ties_beyond_the_sort_cap(isr_ctx, prec):
+    """6,000 identical elements: each coefficient's energy is computed the same
+    way for every copy, so ties of 6,000 survive the reduced-precision
+    transform and the threshold is pinned by refining through every level; the
+    kept set is whole tie groups and the bound holds."""
+    base = synth.field(1, 5, ncomp=1, seed=5)
+    u_np = np.repeat(base, 6000, axis=1)
+    u = torch.from_numpy(u_np).cuda()
+    blob = isr_ctx.compress(u, 5, 1e-3, prec)
+    st = blob.stats
+    assert blob.status == 0 and st["path"] == 1
+    assert st["rel_err"][0] <= 1e-3
+    assert st["kept"][0] % 6000 == 0 and 0 < st["kept"][0] < u_np.size
+    assert blob.to_bytes() == isr_ctx.compress(u, 5, 1e-3, prec).to_bytes()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_mixed_keep_all_round_trip(isr_ctx, prec):
     u_np = synth.field(50, 5, seed=32)
     u = torch.from_numpy(u_np).cuda()

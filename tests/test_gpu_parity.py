@@ -90,6 +90,19 @@ def test_zero_and_constant_fields(isr_ctx):
     _check(*_run(isr_ctx, k, 5, 1e-6))
 
 
+def test_ties_beyond_the_sort_cap(isr_ctx):
+    """6,000 identical elements: every energy value is shared by 6,000
+    coefficients, more than the 4,096 candidates the selection sorts, so the
+    threshold is pinned by refining through every level down to the last bit
+    (levels 4-6 run in one launch); the cut falls between tie groups."""
+    base = synth.field(1, 5, ncomp=1, seed=5)
+    u = np.repeat(base, 6000, axis=1)
+    blob, arr, ref = _run(isr_ctx, u, 5, 1e-3)
+    _check(blob, arr, ref)
+    assert blob.stats["path"] == 1
+    assert ref.comps[0].kept % 6000 == 0 and 0 < ref.comps[0].kept < u.size
+
+
 def test_speculative_window_hit(isr_ctx):
     """4096 elements: a sample of every 32nd element places the window of
     exponent bins that the streaming pass keeps exactly; the threshold falls
