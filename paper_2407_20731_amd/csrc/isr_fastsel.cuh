@@ -112,37 +112,21 @@ DEV void refsel_body(const Job& j, int comp, int L, int vb, int nvb, RefselLds& 
 
 // ---- streaming path: exact window bins, exact totals, level-1 selection ------
 // Every workgroup adds the significands of its share of list 0 (the window
-// energies) to the window bins (integer sums: exact in any order).  The tail
-// turns the per-workgroup integer sums of pass A into exact bins (norm terms
-// anywhere, energies below the window in bins below it), puts the count of
-// energies above the window into bin win_hi and runs the level-1 selection.
+// energies) to the window bins (integer sums: exact in any order); workgroup 0
+// also turns the per-workgroup integer sums of pass A into exact bins (norm
+// terms anywhere, energies below the window in bins below it) and puts the
+// count of energies above the window into bin win_hi.  The tail runs the
+// level-1 selection.
 struct GatherLds {
   u64 red[4][9];
   __int128 r7[4][7];
   int last;
 };
 
-DEV void gather_tail(const Job& j, int comp, GatherLds& X) {
+DEV void gather_tail(const Job& j, int comp) {
   const int tid = threadIdx.x;
   CompState* st = j.st + comp;
   if (st->flags & ST_MISS) return;
-  const int wlo = st->win_lo, whi = st->win_hi;
-  HistBin* gE = j.histE + (size_t)comp * HBINS;
-  HistBin* gN = j.histN + (size_t)comp * HBINS;
-  // totals of pass A's workgroup sums: fields 0..2 norm, 3..5 energy, 6 count
-  __int128 T[7];
-  block_totals<7>(j.slotsA + (size_t)comp * j.gA * 8, j.gA, 8, T, X.r7, tid);
-  if (tid == 0) {
-    __int128 K[3];
-    for (int k = 0; k < 3; ++k) K[k] = T[k];
-    emit_total(gN, K, st->xm_norm, j.xh, -1);
-    for (int k = 0; k < 3; ++k) K[k] = T[3 + k];
-    if (wlo < whi) emit_total(gE, K, wlo - 1023, j.xh, wlo - 1);
-    const u64 above = (u64)T[6];
-    if (above) atomicAdd(&gE[whi].cnt, above);
-  }
-  __threadfence();
-  __syncthreads();
   if (tid < 64) select1_body(j, comp, 0);
   __syncthreads();
   if (tid == 0) {
@@ -166,6 +150,20 @@ DEV void gather_body(const Job& j, int comp, int vb, int nvb, GatherLds& X, bool
   if (st->flags & ST_MISS) return;
   const int wlo = st->win_lo, whi = st->win_hi;
   HistBin* gE = j.histE + (size_t)comp * HBINS;
+  if (vb == 0) {
+    // totals of pass A's workgroup sums: fields 0..2 norm, 3..5 energy, 6 count
+    __int128 T[7];
+    block_totals<7>(j.slotsA + (size_t)comp * j.gA * 8, j.gA, 8, T, X.r7, tid);
+    if (tid == 0) {
+      __int128 K[3];
+      for (int k = 0; k < 3; ++k) K[k] = T[k];
+      emit_total(j.histN + (size_t)comp * HBINS, K, st->xm_norm, j.xh, -1);
+      for (int k = 0; k < 3; ++k) K[k] = T[3 + k];
+      if (wlo < whi) emit_total(gE, K, wlo - 1023, j.xh, wlo - 1);
+      const u64 above = (u64)T[6];
+      if (above) atomicAdd(&gE[whi].cnt, above);
+    }
+  }
   const u64* list = list_ptr(j, comp, 0);
   const u64 nl = st->list_count[0] < j.list_cap ? st->list_count[0] : j.list_cap;
   u64 acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // (cnt, lo, hi) of the three window bins
@@ -208,7 +206,7 @@ DEV void gather_body(const Job& j, int comp, int vb, int nvb, GatherLds& X, bool
     }
   }
   if (!tail || !last_block(j.done + D_GATHER * 8 + comp, &X.last, nvb)) return;
-  gather_tail(j, comp, X);
+  gather_tail(j, comp);
 }
 
 // Per-element kept counts: pass A stored the count of energies above the

@@ -78,7 +78,8 @@ DEV void select1_body(const Job& j, int comp, int sample) {
   int base;
   chunk32(HE, clo, chi, ccnt, base);
   u64 R = Tw, P = 0ull;
-  int bstar = -1;
+  int bstar = -1, lcross = 64;
+  u64 cross_cnt = 0ull;  // this lane's bin of the crossing chunk: its count
   bool found = false;
   for (int l = 0; l < 64 && !Binf; ++l) {
     const u64 cc = bcast64(ccnt, l);
@@ -95,6 +96,8 @@ DEV void select1_body(const Job& j, int comp, int sample) {
     // the crossing chunk, one bin per lane (loads in parallel, then broadcast)
     const int mybin = 32 * l + lane;
     const HistBin mine = (lane < 32 && mybin < HBINS - 1) ? HE[mybin] : HistBin{0ull, 0ull, 0ull};
+    lcross = l;
+    cross_cnt = mine.cnt;
     for (int k = 0; k < 32; ++k) {
       const int bin = 32 * l + k;
       if (bin >= HBINS - 1) break;
@@ -151,12 +154,9 @@ DEV void select1_body(const Job& j, int comp, int sample) {
     }
     return;
   }
-  // counts above b*
-  u64 above = 0ull;
-  for (int k = 0; k < 32; ++k) {
-    const int bin = 32 * lane + k;
-    if (bin > bstar && bin < HBINS - 1) above += HE[bin].cnt;
-  }
+  // counts above b*: the chunks above the crossing one, and the crossing
+  // chunk's bins above b* (bin HBINS - 1 is in neither)
+  u64 above = (lane > lcross ? ccnt : 0ull) + (lane < 32 && 32 * lcross + lane > bstar ? cross_cnt : 0ull);
   above = wave_sum64(above);
   const int s = bstar > 1 ? bstar : 1;
   u64 rlo, rhi;

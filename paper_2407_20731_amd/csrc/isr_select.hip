@@ -53,10 +53,7 @@ __global__ __launch_bounds__(256) void k_scan1(Job j) {
 
 // Per-component tails of the phases above and of the sample pass and pass B
 // (one workgroup per component, after the phase's kernel).
-__global__ __launch_bounds__(256) void k_gather_tail(Job j) {
-  __shared__ GatherLds X;
-  gather_tail(j, blockIdx.x, X);
-}
+__global__ __launch_bounds__(256) void k_gather_tail(Job j) { gather_tail(j, blockIdx.x); }
 
 __global__ __launch_bounds__(256) void k_scan1_tail(Job j) {
   __shared__ ScanLds X;
@@ -75,35 +72,36 @@ __global__ __launch_bounds__(256) void k_scan2(Job j) {
   scan2_body(j, blockIdx.y, blockIdx.x, gridDim.x, X);
 }
 
-// Levels L0..NLEV in one workgroup per component, each refinement followed by
-// its selection.  From level 4 on, the lists hold the members of one level-3
-// sub-bin (a few entries, unless thousands of energies agree in their top 23
-// bits) and the selection has usually been resolved already, so one launch
-// replaces two per level.
-__global__ __launch_bounds__(256) void k_refsel_rest(Job j, int L0) {
+// The selection of level 3, then levels 4..NLEV in the same workgroup (one
+// per component), each refinement followed by its selection.  From level 4 on,
+// the lists hold the members of one level-3 sub-bin (a few entries, unless
+// thousands of energies agree in their top 23 bits) and the selection has
+// usually been resolved already, so one launch replaces seven.
+__global__ __launch_bounds__(256) void k_select_rest(Job j) {
   __shared__ RefselLds X;
   const int comp = blockIdx.x;
-  for (int L = L0; L <= NLEV; ++L) {
+  select_body(j, comp, 3, X.U.S);
+  for (int L = 4; L <= NLEV; ++L) {
+    __syncthreads();
+    __threadfence();
+    __syncthreads();
     if (j.st[comp].resolved) return;
     refine_body(j, comp, L, X.U.h, 0, 1);
     __syncthreads();
     __threadfence();
     __syncthreads();
     select_body(j, comp, L, X.U.S);
-    __syncthreads();
-    __threadfence();
-    __syncthreads();
   }
 }
 
-// the refinement levels 2..NLEV: levels 2 and 3 (over list 0) as a refinement
-// kernel and a selection kernel each, the rest in one launch
+// the refinement levels 2..NLEV: levels 2 and 3 (over list 0) as refinement
+// kernels over the whole grid, the selections of level 2 and of the rest one
+// workgroup per component
 hipError_t launch_refsel(const Job& j, int gx, hipStream_t s) {
-  for (int L = 2; L <= 3; ++L) {
-    hipLaunchKernelGGL(k_refine, dim3(gx, j.ncomp), dim3(256), 0, s, j, L);
-    hipLaunchKernelGGL(k_select, dim3(j.ncomp), dim3(256), 0, s, j, L);
-  }
-  hipLaunchKernelGGL(k_refsel_rest, dim3(j.ncomp), dim3(256), 0, s, j, 4);
+  hipLaunchKernelGGL(k_refine, dim3(gx, j.ncomp), dim3(256), 0, s, j, 2);
+  hipLaunchKernelGGL(k_select, dim3(j.ncomp), dim3(256), 0, s, j, 2);
+  hipLaunchKernelGGL(k_refine, dim3(gx, j.ncomp), dim3(256), 0, s, j, 3);
+  hipLaunchKernelGGL(k_select_rest, dim3(j.ncomp), dim3(256), 0, s, j);
   return hipGetLastError();
 }
 
