@@ -224,12 +224,20 @@ DEV void sampleD_body(const Job& j, int comp, int vb, int nvb, SampleLdsD<N, PRE
     const long long e0 = k * ss * T;
     const int nv = (int)((E - e0) < T ? (E - e0) : T) * n3;
     const double* tile = ub + e0 * n3;
+    // every load of the tile issued before any is used (one memory latency
+    // per tile instead of one per slot)
+    double ut[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int v = 64 * s + lane;
+      ut[s] = v < nv ? __builtin_nontemporal_load(tile + v) : 0.0;
+    }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int v = 64 * s + lane;
       int e, f;
       dense_ef<G>(v, e, f);
-      const double u = v < nv ? __builtin_nontemporal_load(tile + v) : 0.0;
+      const double u = ut[s];
       if (v < nv) {
         const double x = (j.jac ? j.jac[e0 + e] * L.tab.w3[f] : L.tab.w3[f]) * (u * u);
         u2 += x;
