@@ -430,9 +430,10 @@ static FastGrids fast_setup(isr_ctx* c, Job& j, const Sizes& z) {
   const long long stiles = (ftiles + ss - 1) / ss;
   g.gs = (int)std::max<long long>(1, std::min<long long>(64, (stiles + 15) / 16));
   // list passes over ~2 % of the values; few refinement workgroups (each
-  // flushes up to RBINS sub-bins with global atomics)
+  // flushes up to RBINS sub-bins with global atomics: 32 per component beat
+  // 16 and 64 at 100M values)
   g.gl = (int)std::max<long long>(1, std::min<long long>(GATHER_GMAX, (long long)(z.nv >> 17) + 1));
-  g.rgx = std::max(1, std::min(64, (int)(z.nv >> 20) + 1));
+  g.rgx = std::max(1, std::min(32, (int)(z.nv >> 20) + 1));
   g.gsc = scan_grid_elems(j.n_elem);
   return g;
 }
