@@ -501,8 +501,8 @@ DEV void passA_body(const Job& j, int comp, int vb, int nvb, PassALds<N, PREC>& 
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const double x = G::valid(s, lane, ne) ? jw(j.jac, e0 + G::elem(s, lane), L.tab.w3[s][lane]) * (u[s] * u[s]) : 0.0;
-      const double r = xadd_r(an, PN, x);
-      if (r != 0.0) slow_bin(gN, r);
+      double r;
+      if (xadd_left(an, PN, x, r)) slow_bin(gN, r);
       // one slot at a time: interleaving them would hold every slot's
       // temporaries at once and cut the occupancy
       __builtin_amdgcn_sched_barrier(0);

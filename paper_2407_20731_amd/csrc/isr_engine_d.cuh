@@ -351,8 +351,8 @@ DEV void passAD_body(const Job& j, int comp, int vb, int nvb, PassALdsD<N, PREC,
       dense_ef<G>(v, e, f);
       const double u = ut[s];
       const double x = v < nv ? (j.jac ? j.jac[e0 + e] * L.tab.w3[f] : L.tab.w3[f]) * (u * u) : 0.0;
-      const double r = xadd_r(an, PN, x);
-      if (r != 0.0) slow_bin(gN, r);
+      double r;
+      if (xadd_left(an, PN, x, r)) slow_bin(gN, r);
       buf[v] = (float)u;
       __builtin_amdgcn_sched_barrier(0);
     }

@@ -281,8 +281,8 @@ __global__ __launch_bounds__(256, 2) void k_passAL(Job j) {
   for (long long e = (long long)blockIdx.x * 4 + wv; e < E; e += nw) {
     const double jac = j.jac ? j.jac[e] : 1.0;
     fwd_l<G>(ub + e * n3, buf, mt, lane, [&](int q, double x) {
-      const double r = xadd_r(an, PN, (j.jac ? jac * L.tab.w3[q] : L.tab.w3[q]) * (x * x));
-      if (r != 0.0) slow_bin(gN, r);
+      double r;
+      if (xadd_left(an, PN, (j.jac ? jac * L.tab.w3[q] : L.tab.w3[q]) * (x * x), r)) slow_bin(gN, r);
     });
     u32 hc = 0u;
 #pragma unroll 1

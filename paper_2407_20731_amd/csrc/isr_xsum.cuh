@@ -77,6 +77,26 @@ DEV double xadd_r(XAcc& A, const XParm& P, double x) {
   return in ? r2 - q3 : x;
 }
 
+// xadd_r with its result split for the caller's test: true when something is
+// left for the exact global bins, and then `left` is what (the selection
+// that forms it is only needed on that rarely taken branch).
+DEV bool xadd_left(XAcc& A, const XParm& P, double x, double& left) {
+  const bool in = x >= 0.0 && x <= P.M;
+  const double y = in ? x : 0.0;
+  const double q1 = (P.S1 + y) - P.S1;
+  const double r1 = y - q1;
+  const double q2 = (P.S2 + r1) - P.S2;
+  const double r2 = r1 - q2;
+  const double t3 = (P.S3 + r2) - P.S3;
+  const double q3 = t3 > r2 ? t3 - P.u3 : t3;
+  A.a1 = A.a1 + q1;
+  A.a2 = A.a2 + q2;
+  A.a3 = A.a3 + q3;
+  const double r3 = r2 - q3;
+  left = in ? r3 : x;
+  return !in || r3 != 0.0;
+}
+
 // A lane's fixed-order FP64 sum s of at most 2^(h-1) terms in [0, M] (so
 // s <= 2^(m+h-1)) added to the three sums, exactly down to u3; returns what
 // is left for the global bins: the part below u3 (0 <= r < 2 u3), or s itself
