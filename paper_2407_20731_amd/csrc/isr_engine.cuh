@@ -498,9 +498,20 @@ DEV void passA_body(const Job& j, int comp, int vb, int nvb, PassALds<N, PREC>& 
       const long long e1 = (t + nw) * EPW;
       G::load(ub + e1 * n3, (int)((E - e1) < EPW ? (E - e1) : EPW), vec, un, lane);
     }
+    // quadrature weights of the slots (times the element's Jacobian), with the
+    // Jacobian test taken once per tile
+    double wq[NS];
+    if (j.jac) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        wq[s] = G::valid(s, lane, ne) ? j.jac[e0 + G::elem(s, lane)] * L.tab.w3[s][lane] : 0.0;
+    } else {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) wq[s] = L.tab.w3[s][lane];
+    }
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      const double x = G::valid(s, lane, ne) ? jw(j.jac, e0 + G::elem(s, lane), L.tab.w3[s][lane]) * (u[s] * u[s]) : 0.0;
+      const double x = G::valid(s, lane, ne) ? wq[s] * (u[s] * u[s]) : 0.0;
       double r;
       if (xadd_left(an, PN, x, r)) slow_bin(gN, r);
       // one slot at a time: interleaving them would hold every slot's
@@ -513,27 +524,29 @@ DEV void passA_body(const Job& j, int comp, int vb, int nvb, PassALds<N, PREC>& 
       asm volatile("" ::: "memory");
     }
     u32 hc = 0u;
+    if (j.jac) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        wq[s] = G::valid(s, lane, ne) ? j.jac[e0 + G::elem(s, lane)] * L.tab.g3[s][lane] : 0.0;
+    } else {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) wq[s] = L.tab.g3[s][lane];
+    }
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const bool v = G::valid(s, lane, ne);
-      const double en = v ? jw(j.jac, e0 + G::elem(s, lane), L.tab.g3[s][lane]) * (c[s] * c[s]) : 0.0;
+      const double en = v ? wq[s] * (c[s] * c[s]) : 0.0;
       const u64 key = dbits(en);
       const int ex = bits_exp(key);
       const bool hi = v && ex >= whi;
       const bool cp = v && ex < whi && ex >= wlo;
-      if constexpr (EXACT) {
-        double r = xadd_r(ae, PE, (v && ex < wlo) ? en : 0.0);
-        if (hi && ex == HBINS - 1) r = en;  // Inf/NaN: counted in the flag bin
-        if (r != 0.0) slow_bin(gE, r);
-      } else {
-        pe += (v && ex < wlo) ? en : 0.0;
-        if (hi && ex == HBINS - 1) slow_bin(gE, en);
-      }
-      __builtin_amdgcn_sched_barrier(0);
+      const bool nf = hi && ex == HBINS - 1;  // Inf/NaN: counted in the flag bin
+      // the wave votes first: lane flags that stay live across the divergent
+      // branches below would be copied through vector registers on every slot
       const u64 bh = ballot(hi);
+      const u64 bc = ballot(cp);
       hc += (u32)__popcll(bh);
       if (EPW > 1 && hi) atomicAdd(&L.ecnt[wv][G::elem(s, lane)], 1u);
-      const u64 bc = ballot(cp);
       if (bc) {
         const u32 pos = ncap + (u32)__popcll(bc & ((1ull << lane) - 1ull));
         if (cp) {
@@ -546,6 +559,15 @@ DEV void passA_body(const Job& j, int comp, int vb, int nvb, PassALds<N, PREC>& 
           cap_flush(L.key[wv], L.idx[wv], ncap, st, list, lidx, j.list_cap, lane);
         }
       }
+      if constexpr (EXACT) {
+        double r = xadd_r(ae, PE, (v && ex < wlo) ? en : 0.0);
+        if (nf) r = en;
+        if (r != 0.0) slow_bin(gE, r);
+      } else {
+        pe += (v && ex < wlo) ? en : 0.0;
+        if (nf) slow_bin(gE, en);
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
     hi_tot += hc;
     if (EPW == 1) {
