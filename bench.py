@@ -117,7 +117,7 @@ def summarize_trace(trace_csv: str, title: str, command: str) -> str:
             d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
             agg.setdefault(r["Kernel_Name"], []).append(d)
     tot = sum(sum(v) for v in agg.values())
-    out = [f"# {title}", "", "Command (GPU box, repository root):", "", f"    {command}", "",
+    out = [f"# {title}", "", "Command (run on the GPU, from the repository root):", "", f"    {command}", "",
            "Template arguments of the streaming kernels: order N, precision P (0 = FP64, 1 = FP32 MFMA, "
            "2 = BF16-split MFMA), and for the dense-tile kernels (`...D`) the elements per wavefront tile.", "",
            "| Kernel | Calls | Average (us) | Min (us) | Max (us) | Share |", "|---|---|---|---|---|---|"]
@@ -142,7 +142,7 @@ def summarize_counters(csv_paths, title: str, commands) -> str:
                 d = per.setdefault(k, {}).setdefault(r["Counter_Name"], {})
                 d[r["Dispatch_Id"]] = d.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
     names = sorted({c for v in per.values() for c in v})
-    out = [f"# {title}", "", "Commands (GPU box, repository root):", ""] + [f"    {c}" for c in commands] + [
+    out = [f"# {title}", "", "Commands (run on the GPU, from the repository root):", ""] + [f"    {c}" for c in commands] + [
         "", "Per dispatch, averaged over the dispatches of each kernel (device totals; SQ_*_CYCLES in the "
         "counters' own units).", "", "| Kernel | " + " | ".join(names) + " |", "|---" * (len(names) + 1) + "|"]
     for k in sorted(per, key=lambda k: -per[k].get("SQ_INSTS_VALU", {0: 0}).get(min(per[k].get("SQ_INSTS_VALU", {0: 0})), 0)):
@@ -366,8 +366,9 @@ def main() -> int:
         print(json.dumps(rec))
         return 0
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path is single-GPU "
-              "by design; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the library compresses a "
+              "snapshot on one GPU; a sharded run would split the elements over GPUs and all-reduce the integer "
+              "histogram sums)", file=sys.stderr)
         return 2
 
     import torch
