@@ -66,3 +66,24 @@ def test_batch_fp64_matches_oracle(isr_ctx):
             assert arr.comps[c]["tau"] == rc.tau and arr.comps[c]["kept"] == rc.kept
             assert np.array_equal(arr.bitmap[c], rc.bitmap)
             assert np.array_equal(arr.values[c].view(np.uint64), rc.values.view(np.uint64))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batch_window_miss_reruns(isr_ctx, prec):
+    """A snapshot whose sampled elements are scaled far down misses its
+    window inside the persistent launch (every later phase skips it) and is
+    rerun on the general pipeline; it and its batch mates equal their results
+    alone, byte for byte."""
+    rng = np.random.default_rng(13)
+    snaps = _batch(rng, 8, 30, 3000, 900)
+    u = synth.field(4096, 7, ncomp=2, seed=42)
+    u[:, np.arange(4096) % 4 == 0] *= 1e-8
+    snaps.insert(3, (7, 4096, torch.from_numpy(u).cuda()))
+    torch.cuda.synchronize()
+    print(f"[case] batch miss prec={prec} sizes={[(N, E) for N, E, _ in snaps]}", flush=True)
+    blobs = isr_ctx.compress_batch([(x, N, 1e-3) for N, E, x in snaps], prec)
+    assert blobs[3].stats["path"] == 0
+    for (N, E, x), b in zip(snaps, blobs):
+        assert b.status == 0
+        same = b.to_bytes() == isr_ctx.compress(x, N, 1e-3, prec).to_bytes()
+        assert same, (N, E)
