@@ -27,8 +27,11 @@ relative L2 error bound -- as one data-parallel pass over the elements:
 Pins (what each function is checked against, in ``tests/test_oracle_*.py``):
 closed-form GLL rules, scipy's Gauss-Jacobi roots, quadrature exactness,
 numpy's Legendre evaluator, unit coefficients of pure Legendre fields, exact
-keep-all round trip, discrete Parseval, math.fsum / Fraction sums, and brute
-force over all subsets on tiny inputs.  No function here is "parity unpinned".
+keep-all round trip, discrete Parseval (with and without per-element
+Jacobians), norms re-measured with independent weights and exact rationals,
+math.fsum / Fraction sums, brute force over all subsets on tiny inputs,
+hand-computed repair budgets and a repair run to its cap, and bitmap words
+written out by hand for known kept sets.  Every function has such a pin.
 """
 
 from .tables import gll_tables, Tables  # noqa: F401
@@ -38,6 +41,8 @@ from .compress import (  # noqa: F401
     OracleComponent,
     OracleResult,
     compress,
+    repair_budget,
+    repair_loop,
     decompress,
     energies,
     norm_terms,

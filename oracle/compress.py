@@ -153,16 +153,41 @@ class OracleResult:
         return ETOL if any(c.status == ETOL for c in self.comps) else OK
 
 
+def repair_budget(B: float, tol: float, rel: float) -> float:
+    """One rounding repair of the budget: B * (tol/rel)^2 * (1 - 2^-20), in
+    the association (B * ((tol/rel) * (tol/rel))) * (1 - 2^-20).
+
+    If the dropped energy were exactly the squared error, the ratio alone
+    would bring the next cut onto the bound; the extra factor 1 - 2^-20 puts
+    it strictly inside."""
+    f = tol / rel
+    return (B * (f * f)) * REPAIR_SHRINK
+
+
+def repair_loop(cut_and_check, B: float, tol: float):
+    """Cut at budget B and measure the relative error; while it exceeds tol
+    (which only rounding can cause on the exact path), lower B with
+    ``repair_budget`` and cut again, at most REPAIR_MAX times.
+
+    ``cut_and_check(B) -> (rel, payload)``.  Returns
+    ``(payload, B, iterations, status)`` with status ETOL when the last
+    measured error still exceeds tol."""
+    it = 0
+    while True:
+        rel, payload = cut_and_check(B)
+        if rel <= tol or it >= REPAIR_MAX:
+            break
+        B = repair_budget(B, tol, rel)
+        it += 1
+    return payload, B, it, (OK if rel <= tol else ETOL)
+
+
 def _compress_component(uc, T, tol, jac, keep_arrays):
     coef = forward(uc, T.A)
     e = energies(coef, T.g3, jac)
     U2 = exact_sum(norm_terms(uc, T.w3, jac))
-    if tol < 0:
-        B = 0.0
-    else:
-        B = (tol * tol) * U2
-    it = 0
-    while True:
+
+    def cut_and_check(B):
         if tol < 0:
             tau, S = 0.0, 0.0
         else:
@@ -173,15 +198,18 @@ def _compress_component(uc, T, tol, jac, keep_arrays):
         d = uc - recon
         err2 = exact_sum(norm_terms(d, T.w3, jac))
         rel = math.sqrt(err2 / U2) if U2 > 0 else 0.0
-        if tol < 0 or rel <= tol or it >= REPAIR_MAX:
-            break
-        f = tol / rel
-        B = (B * (f * f)) * REPAIR_SHRINK
-        it += 1
+        return rel, (tau, S, keep, recon, err2, rel)
+
+    if tol < 0:
+        # keep every coefficient: no threshold, nothing to repair
+        rel, payload = cut_and_check(0.0)
+        B, it, status = 0.0, 0, OK
+    else:
+        payload, B, it, status = repair_loop(cut_and_check, (tol * tol) * U2, tol)
+    tau, S, keep, recon, err2, rel = payload
     counts = keep.reshape(keep.shape[0], -1).sum(axis=1).astype(np.uint64)
     elem_ptr = np.zeros(keep.shape[0] + 1, dtype=np.uint64)
     np.cumsum(counts, out=elem_ptr[1:])
-    status = OK if (tol < 0 or rel <= tol) else ETOL
     return OracleComponent(
         U2=U2, B=B, tau=tau, dropped=S, err2=err2, rel_err=rel,
         kept=int(elem_ptr[-1]), bitmap=pack_bitmap(keep), elem_ptr=elem_ptr,
