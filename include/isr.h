@@ -170,6 +170,34 @@ const char *isr_last_error(void);
  * tol, bad precision, non-finite field values), ISR_ENOMEM, ISR_EDEVICE. */
 int isr_compress(isr_ctx *ctx, const isr_field *f, isr_blob **out, isr_stats *st);
 
+/* ---- allocation-free compression ----------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * compression as isr_compress (same kernels, same result, byte for byte),
+ * but the call allocates nothing: no hipMalloc / hipFree, no host or pinned
+ * allocation.  Its scratch is a fixed device array of the library,
+ * ISR_NOALLOC_SCRATCH_BYTES per GPU, held by every GPU the library runs on
+ * until the process ends; a request whose scratch exceeds it is refused with
+ * ISR_ENOMEM (about 20 bytes per value plus 2.1 MB: at N = 7 with 3
+ * components, up to about 4,200 elements).  The blob is written to the caller's
+ * buffer.
+ *   d_out      DEVICE pointer, 256-byte aligned, out_cap bytes; receives the
+ *              serialized blob (the bytes isr_blob_to_host would give, layout
+ *              below).  out_cap must hold the worst case (every coefficient
+ *              kept): 48 + 64 ncomp + 8 ncomp n_elem W + 8 ncomp (n_elem + 1)
+ *              + ncomp n_elem n^3 value_bytes; otherwise ISR_EINVAL.
+ *   out_bytes  receives the blob's size (on ISR_EINVAL for a short buffer:
+ *              the size required).  May be NULL.
+ * Blocking: returns once the blob and *st are complete.  Returns ISR_OK or
+ * ISR_ETOL (the blob is written in both cases), else an error as
+ * isr_compress.  Every call on one GPU uses the same scratch array, which
+ * keeps the last call's contents (the pipeline clears what must start at
+ * zero); the library runs these calls one at a time per GPU, since calls
+ * that overlapped on one GPU would race on it. */
+#define ISR_NOALLOC_SCRATCH_BYTES (128ull << 20)
+int isr_compress_noalloc(isr_ctx *ctx, const isr_field *f, void *d_out, uint64_t out_cap, uint64_t *out_bytes,
+                         isr_stats *st);
+
 /* Compress several snapshots (orders may differ) in one batched launch
  * sequence: one persistent launch when every snapshot has order 5, 7 or 9
  * (FP32 / BF16: with the tile shapes the persistent kernel holds, the

@@ -280,6 +280,13 @@ size_t fbatch_lds_bf16();
 int fbatch_resident_fp32(size_t lds);
 int fbatch_resident_bf16(size_t lds);
 
+// Allocation-free entry point (isr_noalloc.hip): header bytes of a
+// serialized blob (48 + 64 per component) written by a kernel, and the
+// per-device lookup of the fixed scratch array's address.
+constexpr int ISR_NOALLOC_HDR_MAX = 48 + 64 * 8;
+hipError_t launch_put_bytes(const void* src, int n, void* dst, hipStream_t s);
+int noalloc_init(int device);
+
 // Host tables (isr_tables.cpp): correctly rounded FP64 values.
 struct HostTables {
   int N;

@@ -39,6 +39,18 @@ static int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+namespace isr {
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+}  // namespace isr
+
 #define HIPCHK(expr)                                                                      \
   do {                                                                                    \
     hipError_t e_ = (expr);                                                               \
@@ -227,7 +239,7 @@ struct isr_ctx {
   int max_inflight = 8;
   std::atomic<int> tile[ISR_MAX_ORDER + 1][3];  // tile shape per (order, precision); -1 = built-in
   std::string tune_path;           // tile table file (read at create, written by the autotuner)
-  CompState* st_host = nullptr;  // pinned
+  CompState* st_host = nullptr;  // pinned state copy of isr_compress_noalloc (under mu)
   std::mutex host_mu;            // pool of pinned per-request state buffers
   std::vector<CompState*> host_all, host_free;
 };
@@ -347,7 +359,18 @@ Sizes plan_sizes(const isr_field* f, int tile) {
 
 }  // namespace isr
 
-static Job make_job(isr_ctx* c, const isr_field* f, const Sizes& z, char* scratch, isr_blob* b) {
+// Device addresses of a blob's sections (per-component value offsets, bitmaps,
+// offset tables, values).
+struct BlobPtrs {
+  u64* voff;
+  u64* bitmap;
+  u64* elem_ptr;
+  void* values;
+};
+
+static BlobPtrs blob_ptrs(const isr_blob* b) { return {b->voff(), b->bitmap(), b->elem_ptr(), b->values()}; }
+
+static Job make_job(isr_ctx* c, const isr_field* f, const Sizes& z, char* scratch, const BlobPtrs& bp) {
   Job j;
   std::memset(&j, 0, sizeof(j));
   const long long n = f->order + 1, n3 = n * n * n;
@@ -384,10 +407,10 @@ static Job make_job(isr_ctx* c, const isr_field* f, const Sizes& z, char* scratc
     j.chunk = (u64*)(scratch + z.off_chunk);
     j.nchunk = (f->n_elem + 1023) / 1024;
   }
-  j.bitmap = b->bitmap();
-  j.elem_ptr = b->elem_ptr();
-  j.values = b->values();
-  j.voff = b->voff();
+  j.bitmap = bp.bitmap;
+  j.elem_ptr = bp.elem_ptr;
+  j.values = bp.values;
+  j.voff = bp.voff;
   return j;
 }
 
@@ -642,6 +665,26 @@ void task_release(Task* t) {
   t->hs = nullptr;
 }
 
+// Rounding repair after a finished pass: for every component whose measured
+// error exceeds tol, lower its budget to B (tol/rel)^2 (1 - 2^-20); keep the
+// others' budgets (which reproduces their results).  At most 4 repairs.
+// Returns whether another pass is needed.
+static bool plan_repair(const isr_field* f, const CompState* hs, int iters, double* Bov) {
+  bool again = false;
+  if (f->tol >= 0.0 && iters < 4) {
+    for (int k = 0; k < f->ncomp; ++k) {
+      if (hs[k].rel > f->tol) {
+        const double fr = f->tol / hs[k].rel;
+        Bov[k] = (hs[k].B * (fr * fr)) * (1.0 - 0x1p-20);
+        again = true;
+      } else {
+        Bov[k] = hs[k].B;  // unchanged, reproduces the same result
+      }
+    }
+  }
+  return again;
+}
+
 // Validate, allocate and enqueue the whole pipeline on stream s.  ISR_ENOMEM
 // when the request does not fit the HBM budget right now.
 int task_begin(isr_ctx* c, const isr_field* f, hipStream_t s, bool timing, Task* t) {
@@ -665,7 +708,7 @@ int task_begin(isr_ctx* c, const isr_field* f, hipStream_t s, bool timing, Task*
     task_release(t);
     return fail(ISR_EDEVICE, "could not create host state or event");
   }
-  t->j = make_job(c, f, t->z, t->scratch, t->b);
+  t->j = make_job(c, f, t->z, t->scratch, blob_ptrs(t->b));
   t->fast = t->z.fast;
   t->timing = timing;
   if (timing)
@@ -718,18 +761,7 @@ int task_step(Task* t, isr_blob** out) {
     }
   }
   // rounding repair: lower B where the measured error exceeds tol
-  bool again = false;
-  if (f->tol >= 0.0 && t->iters < 4) {
-    for (int k = 0; k < f->ncomp; ++k) {
-      if (hs[k].rel > f->tol) {
-        const double fr = f->tol / hs[k].rel;
-        t->j.Bov[k] = (hs[k].B * (fr * fr)) * (1.0 - 0x1p-20);
-        again = true;
-      } else {
-        t->j.Bov[k] = hs[k].B;  // unchanged, reproduces the same result
-      }
-    }
-  }
+  const bool again = plan_repair(f, hs, t->iters, t->j.Bov);
   if (again) {
     ++t->iters;
     rc = task_enqueue(t);
@@ -849,7 +881,7 @@ static int run_batch_stream(isr_ctx* c, const isr_field* fs, int count, isr_blob
       cleanup();
       return fail(ISR_ENOMEM, "batch of %d snapshots does not fit the HBM budget", count);
     }
-    x.j = make_job(c, &fs[i], x.z, x.scratch, x.b);
+    x.j = make_job(c, &fs[i], x.z, x.scratch, blob_ptrs(x.b));
     x.g = fast_setup(c, x.j, x.z);
   }
   // pairs of the largest snapshots first in every phase: their passes start
@@ -1052,7 +1084,7 @@ int run_batch(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_s
       cleanup();
       return fail(ISR_ENOMEM, "batch of %d snapshots does not fit the HBM budget", count);
     }
-    x.j = make_job(c, &fs[i], x.z, x.scratch, x.b);
+    x.j = make_job(c, &fs[i], x.z, x.scratch, blob_ptrs(x.b));
   }
   // pairs and items of every phase
   std::vector<int> psnap, pcomp;
@@ -1277,7 +1309,9 @@ int isr_create(const isr_config* cfg, isr_ctx** out) {
   }
   int rc = upload_tables(c.get());
   if (rc) return rc;
-  HIPCHK(hipHostMalloc((void**)&c->st_host, sizeof(CompState) * ISR_MAX_COMP * 64, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&c->st_host, sizeof(CompState) * ISR_MAX_COMP, hipHostMallocDefault));
+  rc = isr::noalloc_init(c->device);  // address of the allocation-free entry point's scratch on this GPU
+  if (rc) return rc;
   c->sched.reset(new isr::Scheduler(c.get()));
   *out = c.release();
   return ISR_OK;
@@ -1599,3 +1633,90 @@ int isr_gll_tables(int32_t order, double* xi, double* w, double* V, double* A, d
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// allocation-free compression (isr_compress_noalloc)
+
+namespace isr {
+
+int run_compress_noalloc(isr_ctx* c, const isr_field* f, char* scratch, size_t scratch_cap, void* d_out,
+                         uint64_t out_cap, uint64_t* out_bytes, isr_stats* st) {
+  const double t0 = now_s();
+  int rc = check_field(f);
+  if (rc) return rc;
+  if (!d_out) return fail(ISR_EINVAL, "output pointer is NULL");
+  if (((uintptr_t)d_out) & 255) return fail(ISR_EINVAL, "output pointer is not 256-byte aligned");
+  std::lock_guard<std::mutex> g(c->mu);
+  const Sizes z = plan_sizes(f, ctx_tile(c, f->order, f->precision));
+  const int nc = f->ncomp;
+  const size_t hb = isr_blob::HDR + isr_blob::CHDR * (size_t)nc;
+  const size_t bm = (size_t)nc * f->n_elem * z.W * 8, ep = (size_t)nc * (f->n_elem + 1) * 8;
+  const size_t need = hb + bm + ep + (size_t)nc * z.nv * z.vbytes;
+  if (out_bytes) *out_bytes = need;
+  if (out_cap < need)
+    return fail(ISR_EINVAL, "output buffer of %llu bytes is smaller than the worst-case blob of %zu bytes",
+                (unsigned long long)out_cap, need);
+  // the per-component value offsets live right after the scratch proper
+  const size_t voff_at = (z.scratch_bytes + 255) & ~size_t(255);
+  if (voff_at + 256 > scratch_cap)
+    return fail(ISR_ENOMEM, "request needs %zu bytes of scratch; the allocation-free entry point holds %zu",
+                voff_at + 256, scratch_cap);
+  char* out = (char*)d_out;
+  const BlobPtrs bp{(u64*)(scratch + voff_at), (u64*)(out + hb), (u64*)(out + hb + bm), out + hb + bm + ep};
+  Job j = make_job(c, f, z, scratch, bp);
+  hipStream_t s = (hipStream_t)f->stream;
+  CompState* hs = c->st_host;
+  bool fast = z.fast;
+  int iters = 0;
+  for (;;) {
+    rc = enqueue_pipeline(c, j, z, s, nullptr, fast);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(hs, j.st, sizeof(CompState) * nc, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int flags = 0;
+    for (int k = 0; k < nc; ++k) flags |= hs[k].flags;
+    if (fast && (flags & ST_MISS)) {  // threshold outside the sampled window: general pipeline
+      fast = false;
+      j.sample_stride = 0;
+      continue;
+    }
+    rc = status_from_flags(flags);
+    if (rc) return rc;
+    if (!plan_repair(f, hs, iters, j.Bov)) break;
+    ++iters;
+  }
+  // describe the result in a blob record on the stack (no device memory of
+  // its own) to form the header
+  isr_blob b;
+  b.ctx = c;
+  b.order = f->order;
+  b.ncomp = nc;
+  b.n_elem = f->n_elem;
+  b.vbytes = z.vbytes;
+  b.W = z.W;
+  b.tol = f->tol;
+  b.precision = f->precision;
+  isr_stats tmp;
+  std::memset(&tmp, 0, sizeof(tmp));
+  fill_stats(&b, hs, &tmp);
+  bool within = true;
+  if (f->tol >= 0.0)
+    for (int k = 0; k < nc; ++k) within = within && !(hs[k].rel > f->tol);
+  b.status = within ? ISR_OK : ISR_ETOL;
+  char hdr[isr_blob::HDR + isr_blob::CHDR * ISR_MAX_COMP];
+  put_hdr(&b, hdr);
+  HIPCHK(launch_put_bytes(hdr, (int)hb, d_out, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (out_bytes) *out_bytes = b.serialized();
+  tmp.repair_iters = iters;
+  tmp.path = fast ? 1 : 0;
+  tmp.status = b.status;
+  tmp.t_submit = t0;
+  tmp.t_start = t0;
+  tmp.t_done = now_s();
+  if (st) *st = tmp;
+  if (!within) fail(ISR_ETOL, "relative error above tol after %d repairs", iters);
+  return b.status;
+}
+
+}  // namespace isr

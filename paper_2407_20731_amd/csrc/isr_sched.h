@@ -74,6 +74,13 @@ int run_compress(isr_ctx* c, const isr_field* f, isr_blob** out, isr_stats* st);
 int run_batch(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_stats* st);
 int run_batch_sequential(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_stats* st);
 uint64_t request_footprint(const isr_field* f);
+// isr_compress_noalloc: one compression with caller-provided scratch (at most
+// scratch_cap bytes, used from its start) and the serialized blob written to
+// d_out; no allocation of any kind.
+int run_compress_noalloc(isr_ctx* c, const isr_field* f, char* scratch, size_t scratch_cap, void* d_out,
+                         uint64_t out_cap, uint64_t* out_bytes, isr_stats* st);
+// set the calling thread's isr_last_error() text and return code
+int set_error(int code, const char* fmt, ...);
 int ctx_device(const isr_ctx* c);
 int ctx_max_inflight(const isr_ctx* c);
 uint64_t ctx_budget(const isr_ctx* c);

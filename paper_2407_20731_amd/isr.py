@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH):
         "isr_version": (C.c_char_p, []),
         "isr_compress": (I32, [P, C.POINTER(isr_field), C.POINTER(P), C.POINTER(isr_stats)]),
         "isr_compress_batch": (I32, [P, C.POINTER(isr_field), I32, C.POINTER(P), C.POINTER(isr_stats)]),
+        "isr_compress_noalloc": (I32, [P, C.POINTER(isr_field), P, U64, C.POINTER(U64), C.POINTER(isr_stats)]),
         "isr_submit": (I32, [P, C.POINTER(isr_field), C.POINTER(U64)]),
         "isr_poll": (I32, [P, U64, I32, C.POINTER(P), C.POINTER(isr_stats)]),
         "isr_decompress": (I32, [P, P, P, I32, P]),
@@ -325,6 +326,21 @@ class Context:
         if rc not in (OK, ETOL):
             _check(rc, "isr_compress")
         return Blob(self, h.value, _stats_dict(st, f.ncomp), rc)
+
+    def compress_noalloc(self, u, order: int, tol: float, out, precision="fp64", stream=None):
+        """Allocation-free compression into `out` (a uint8 CUDA tensor of at
+        least the worst-case blob size, 256-byte aligned).  Returns
+        (status, blob bytes, stats dict); the serialized blob is out[:bytes]."""
+        f = self._field(u, order, tol, precision, None, stream)
+        if not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != torch.uint8 or not out.is_contiguous():
+            raise TypeError("out must be a contiguous uint8 CUDA tensor")
+        n = C.c_uint64()
+        st = isr_stats()
+        rc = load_library().isr_compress_noalloc(self._h, C.byref(f), C.c_void_p(out.data_ptr()), out.numel(),
+                                                 C.byref(n), C.byref(st))
+        if rc not in (OK, ETOL):
+            _check(rc, "isr_compress_noalloc")
+        return rc, n.value, _stats_dict(st, f.ncomp)
 
     def compress_batch(self, fields: Sequence[tuple], precision="fp64", stream=None) -> List[Blob]:
         """fields: sequence of (u, order, tol)."""

@@ -1,0 +1,73 @@
+"""The allocation-free entry point (isr_compress_noalloc) against isr_compress.
+
+Two calls in a row on the library's fixed scratch array, the second with a
+smaller input, each compared byte for byte with the serialized blob that
+isr_compress gives for the same request (same kernels, so the same result);
+the FP64 results are also checked against the oracle.  Plus the refusals: a
+buffer below the worst-case blob size and a request whose scratch exceeds
+the array.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _worst_case_bytes(E, order, ncomp, vbytes):
+    n = order + 1
+    W = (n ** 3 + 63) // 64
+    return 48 + 64 * ncomp + 8 * ncomp * E * W + 8 * ncomp * (E + 1) + ncomp * E * n ** 3 * vbytes
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_noalloc_equals_compress_on_two_calls(isr_ctx, prec):
+    from paper_2407_20731_amd import isr
+    vb = 8 if prec == "fp64" else 4
+    cases = [(2000, 7, 1e-3, 401), (333, 7, 1e-3, 402), (700, 5, 1e-2, 403)]  # second call smaller
+    cap = max(_worst_case_bytes(E, N, 3, vb) for E, N, _, _ in cases)
+    out = torch.empty(cap + 4096, dtype=torch.uint8, device="cuda")
+    assert out.data_ptr() % 256 == 0
+    for E, N, tol, seed in cases:
+        print(f"[case] noalloc {prec} E={E} N={N} tol={tol}", flush=True)
+        u_np = synth.field(E, N, seed=seed)
+        u = torch.from_numpy(u_np).cuda()
+        out.fill_(0xA5)  # stale bytes everywhere: the call must write all it reports
+        rc, nbytes, st = isr_ctx.compress_noalloc(u, N, tol, out, prec)
+        torch.cuda.synchronize()
+        blob = isr_ctx.compress(u, N, tol, prec)
+        want = blob.to_bytes()
+        assert rc == blob.status == isr.OK
+        assert nbytes == len(want) == st["blob_bytes"], (nbytes, len(want))
+        got = out[:nbytes].cpu().numpy().tobytes()
+        assert got == want
+        assert st["kept"] == blob.stats["kept"] and st["tau"] == blob.stats["tau"]
+        assert st["rel_err"] == blob.stats["rel_err"] and st["path"] == blob.stats["path"]
+        if prec == "fp64":
+            arr = isr.parse_blob(got)
+            ref = oracle.compress(u_np, N, tol, keep_arrays=True)
+            for c, rc_ in enumerate(ref.comps):
+                assert arr.comps[c]["tau"] == rc_.tau and arr.comps[c]["kept"] == rc_.kept
+                assert np.array_equal(arr.bitmap[c], rc_.bitmap)
+                assert np.array_equal(arr.values[c].view(np.uint64), rc_.values.view(np.uint64))
+        blob.free()
+
+
+def test_noalloc_refusals(isr_ctx):
+    from paper_2407_20731_amd import isr
+    u = torch.from_numpy(synth.field(100, 7, seed=404)).cuda()
+    need = _worst_case_bytes(100, 7, 3, 8)
+    small = torch.empty(need - 8, dtype=torch.uint8, device="cuda")
+    with pytest.raises(isr.IsrError) as e:
+        isr_ctx.compress_noalloc(u, 7, 1e-3, small, "fp64")
+    assert e.value.code == isr.EINVAL and "worst-case" in str(e.value)
+    # 6,000 elements of order 7, 3 components: ~185 MB of scratch, above the array
+    big = torch.zeros((3, 6000, 8, 8, 8), dtype=torch.float64, device="cuda")
+    out = torch.empty(_worst_case_bytes(6000, 7, 3, 4), dtype=torch.uint8, device="cuda")
+    with pytest.raises(isr.IsrError) as e:
+        isr_ctx.compress_noalloc(big, 7, 1e-3, out, "bf16")
+    assert e.value.code == isr.ENOMEM and "scratch" in str(e.value)
