@@ -23,11 +23,15 @@
  *      it lowers B by (tol/rel)^2 * (1 - 2^-20) and repeats 3-5 (at most 4
  *      times; then ISR_ETOL).
  *
- * All sums that decide the threshold (U2, S, err2) are the correctly rounded
- * values of the exact sums of their FP64 terms, so results do not depend on
- * scheduling.  With ISR_PREC_FP64 the transforms use one fixed evaluation
- * order (see isr_forward), so every coefficient, energy and threshold is
- * reproducible bit for bit by a CPU implementation of the same definition.
+ * U2 is the correctly rounded value of the exact sum of its FP64 terms on
+ * every path.  With ISR_PREC_FP64 so are S and err2, and the transforms use
+ * one fixed evaluation order (see isr_forward), so every coefficient, energy
+ * and threshold is reproducible bit for bit by a CPU implementation of the
+ * same definition.  With ISR_PREC_FP32 / ISR_PREC_BF16, whose energies and
+ * reconstruction carry the transform error, each lane adds its energy and
+ * error terms in a fixed FP64 order and only the lane totals are combined
+ * exactly: S and err2 are deterministic (the same alone, in a batch or in
+ * the serving mix) but not correctly rounded (relative error below 1e-12).
  *
  * Conventions
  *   - Every function returns an int status (ISR_OK or a negative ISR_E*),
@@ -102,11 +106,21 @@ typedef struct {
  *   tol          relative mass-weighted L2 bound per component, >= 0; a
  *                negative tol keeps every coefficient (lossless transform).
  *   precision    ISR_PREC_*.
+ *   flags        0, or ISR_FIELD_COPY (isr_submit only): copy-on-submit.
+ *                isr_submit copies the field (and elem_jac) into the
+ *                library's HBM arena on `stream` before it returns, so the
+ *                caller may overwrite them with work enqueued on `stream`
+ *                right away (from the host or another stream: after
+ *                synchronising with `stream`).  The copy counts against the
+ *                HBM budget until the request completes; when the budget
+ *                cannot hold it at submit time, isr_submit returns
+ *                ISR_ENOMEM.  Without the flag the field is borrowed.
  *   elem_jac     optional DEVICE pointer to n_elem positive FP64 Jacobians of
  *                affine elements (constant per element); NULL means 1.
  *   stream       hipStream_t on which `field` was produced; the library's
  *                work is ordered after it.
  */
+#define ISR_FIELD_COPY 1
 typedef struct {
   const double *field;
   int64_t n_elem;
@@ -115,7 +129,7 @@ typedef struct {
   int64_t comp_stride;
   double tol;
   int32_t precision;
-  int32_t reserved;
+  int32_t flags;
   const double *elem_jac;
   void *stream;
 } isr_field;
@@ -184,7 +198,7 @@ int isr_compress(isr_ctx *ctx, const isr_field *f, isr_blob **out, isr_stats *st
  *   d_out      DEVICE pointer, 256-byte aligned, out_cap bytes; receives the
  *              serialized blob (the bytes isr_blob_to_host would give, layout
  *              below).  out_cap must hold the worst case (every coefficient
- *              kept): 48 + 64 ncomp + 8 ncomp n_elem W + 8 ncomp (n_elem + 1)
+ *              kept): 56 + 64 ncomp + 8 ncomp n_elem W + 8 ncomp (n_elem + 1)
  *              + ncomp n_elem n^3 value_bytes; otherwise ISR_EINVAL.
  *   out_bytes  receives the blob's size (on ISR_EINVAL for a short buffer:
  *              the size required).  May be NULL.
@@ -200,9 +214,10 @@ int isr_compress_noalloc(isr_ctx *ctx, const isr_field *f, void *d_out, uint64_t
 
 /* Compress several snapshots (orders may differ) in one batched launch
  * sequence: one persistent launch when every snapshot has order 5, 7 or 9
- * (FP32 / BF16: with the tile shapes the persistent kernel holds, the
- * built-in ones, and at least 8 snapshots), else one pipeline per snapshot on
- * the scheduler's streams.  outs[i] / st[i] as in isr_compress; returns the first non-OK
+ * (FP32 / BF16: at least 8 snapshots, each with the tile shape the context
+ * holds for its order and precision -- built-in or set by isr_autotune /
+ * isr_set_tile; the kernel holds every candidate shape), else one pipeline
+ * per snapshot on the scheduler's streams.  outs[i] / st[i] as in isr_compress; returns the first non-OK
  * status (each st[i].status holds its own).  Footprint of the whole batch must
  * fit the budget (ISR_ENOMEM otherwise). */
 int isr_compress_batch(isr_ctx *ctx, const isr_field *fs, int32_t count, isr_blob **outs,
@@ -212,8 +227,10 @@ int isr_compress_batch(isr_ctx *ctx, const isr_field *fs, int32_t count, isr_blo
  * Requests are admitted to the device while their footprint fits the HBM
  * budget and fewer than max_inflight are resident; later arrivals join the
  * running ones (continuous batching).  The field must stay unchanged until
- * isr_poll reports completion.  Errors as isr_compress (argument checks
- * only; ISR_ENOMEM if the request alone exceeds the budget). */
+ * isr_poll reports completion, unless f->flags holds ISR_FIELD_COPY
+ * (copy-on-submit, above).  Errors as isr_compress (argument checks only;
+ * ISR_ENOMEM if the request alone exceeds the budget, or its copy does not
+ * fit it now). */
 int isr_submit(isr_ctx *ctx, const isr_field *f, uint64_t *req);
 
 /* Poll a request: ISR_PENDING while running; otherwise the request's final
@@ -224,9 +241,12 @@ int isr_poll(isr_ctx *ctx, uint64_t req, int32_t wait_ms, isr_blob **out, isr_st
 
 /* Reconstruct the nodal field from a blob into d_out (DEVICE, same layout as
  * the input with comp_stride = n_elem * n^3), FP64 (out_prec ISR_PREC_FP64)
- * or FP32 (ISR_PREC_FP32).  Uses the FP64 inverse transform in the fixed
- * order (kept values are widened to FP64 first).  Enqueued on `stream`; the
- * call returns after enqueueing.  Errors: ISR_EINVAL, ISR_EDEVICE. */
+ * or FP32 (ISR_PREC_FP32).  The inverse is the one whose result the
+ * compression measured, so the blob's rel_err is the error of this output:
+ * FP64 blobs use the FP64 inverse in the fixed order (that of isr_forward,
+ * with V); FP32 / BF16 blobs repeat, bit for bit, the MFMA inverse of the
+ * engine that compressed them (recorded in the blob).  Enqueued on `stream`;
+ * the call returns after enqueueing.  Errors: ISR_EINVAL, ISR_EDEVICE. */
 int isr_decompress(isr_ctx *ctx, const isr_blob *b, void *d_out, int32_t out_prec, void *stream);
 
 /* Forward transform only (no truncation): coefficients c[comp][e][r][q][p]
@@ -238,9 +258,11 @@ int isr_decompress(isr_ctx *ctx, const isr_blob *b, void *d_out, int32_t out_pre
 int isr_forward(isr_ctx *ctx, const isr_field *f, void *d_coef);
 
 /* Blob queries and (de)serialisation.  Serialized layout (little endian):
- *   "ISR1", u32 version=1, i32 order, i32 ncomp, i64 n_elem, i32 value_bytes
+ *   "ISR1", u32 version=2, i32 order, i32 ncomp, i64 n_elem, i32 value_bytes
  *   (8 or 4), i32 words_per_elem W = ceil(n^3/64), f64 tol, i32 precision,
- *   i32 status; then per component: f64 U2, B, tau, dropped, err2, rel_err,
+ *   i32 status, i32 engine (FP32 / BF16: 0 general passes, 1 wave-tile or
+ *   large-order engine, 2 dense-tile engine; 0 for FP64), i32 tile (the
+ *   dense tile, else 0); then per component: f64 U2, B, tau, dropped, err2, rel_err,
  *   u64 kept, u64 values_offset; then all bitmaps [ncomp][n_elem][W] u64 (bit
  *   f = p + n q + n^2 r of element e set iff kept), all offset tables
  *   [ncomp][n_elem + 1] u64 (per component, starting at 0), all kept values

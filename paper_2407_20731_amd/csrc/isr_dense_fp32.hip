@@ -7,13 +7,17 @@ namespace isr {
 
 hipError_t launch_dense_fp32(int kind, const Job& j, int gx, hipStream_t s) { return launch_dense_prec<P_FP32>(kind, j, gx, s); }
 
+hipError_t launch_decomp_dense_fp32(const Job& j, int gx, hipStream_t s, void* out, int out_fp64) {
+  return launch_decompD_prec<P_FP32>(j, gx, s, out, out_fp64);
+}
+
 int resident_dense_fp32(int kind, int order, int tile) { return resident_dense_prec<P_FP32>(kind, order, tile); }
 
 hipError_t launch_fbatch_fp32(const BatchCtl& B, int grid, size_t lds, hipStream_t s) {
   return launch_fbatch_prec<P_FP32>(B, grid, lds, s);
 }
 
-size_t fbatch_lds_fp32() { return fbatch_lds_prec<P_FP32>(); }
+size_t fbatch_lds_fp32(int order, int tile) { return fbatch_lds_prec<P_FP32>(order, tile); }
 
 int fbatch_resident_fp32(size_t lds) { return fbatch_resident_prec<P_FP32>(lds); }
 

@@ -811,8 +811,83 @@ __global__ __launch_bounds__(256, ISR_FAST_MINB) void k_passB(Job j) {
   passB_body<N, PREC>(j, blockIdx.y, blockIdx.x, gridDim.x, L, false);
 }
 
+// ---- decompress of blobs made by this engine --------------------------------------
+// The blob's kept values go back into the slots pass B took them from, and the
+// same inverse runs on them, so that the reconstruction is the one whose
+// error pass B measured, bit for bit (FP32 / BF16 blobs).  One tile per
+// wavefront, tiles of every component in turn.
+template <int N, int PREC>
+__global__ __launch_bounds__(256) void k_decompW(Job j, void* out, int out_fp64) {
+  typedef Eng<N, PREC> G;
+  constexpr int n = G::n, n2 = G::n2, n3 = G::n3, NS = G::NS, EPW = G::EPW, W = G::W;
+  static_assert(EPW * W <= 16, "tile bitmap fits the LDS slot");
+  __shared__ typename G::wt buf[4][G::LDSW];
+  __shared__ u64 bm[4][16];
+  __shared__ u32 wp[4][16];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  typename G::Mats mt;
+  G::init(mt, j.tab, lane);
+  const long long E = j.n_elem, tiles = (E + EPW - 1) / EPW, total = tiles * j.ncomp;
+  for (long long tk = (long long)blockIdx.x * 4 + wv; tk < total; tk += (long long)gridDim.x * 4) {
+    const int comp = (int)(tk / tiles);
+    const long long e0 = (tk % tiles) * EPW;
+    const int ne = (int)((E - e0) < EPW ? (E - e0) : EPW);
+    const u64* gbm = j.bitmap + ((size_t)comp * E + e0) * W;
+    const u64* eptr = j.elem_ptr + (size_t)comp * (E + 1);
+    const u64 voff = j.voff[comp];
+    if (lane < ne * W) bm[wv][lane] = gbm[lane];
+    asm volatile("" ::: "memory");
+    if (lane < ne * W) {
+      const int ee = lane / W, w = lane % W;
+      u32 pre = 0u;
+      for (int k = 0; k < w; ++k) pre += (u32)__popcll(bm[wv][ee * W + k]);
+      wp[wv][lane] = pre;
+    }
+    asm volatile("" ::: "memory");
+    double cm[NS], ut[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      cm[s] = 0.0;
+      if (!G::valid(s, lane, ne)) continue;
+      const int PI = G::pencil(s, lane), ax = G::axis(s, lane);
+      const int ee = PI / n2, f = ax * n2 + PI % n2, wi = ee * W + (f >> 6);
+      const u64 wd = bm[wv][wi];
+      if ((wd >> (f & 63)) & 1ull) {
+        const u64 pos = voff + eptr[e0 + ee] + wp[wv][wi] + (u64)__popcll(wd & ((1ull << (f & 63)) - 1ull));
+        cm[s] = j.vbytes == 8 ? ((const double*)j.values)[pos] : (double)((const float*)j.values)[pos];
+      }
+    }
+    G::inverse(cm, ut, buf[wv], mt, j.tab, lane);
+    const size_t ob = ((size_t)comp * E + e0) * n3;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      if (!G::valid(s, lane, ne)) continue;
+      const size_t o = ob + (size_t)G::pencil(s, lane) * n + G::axis(s, lane);
+      if (out_fp64)
+        ((double*)out)[o] = ut[s];
+      else
+        ((float*)out)[o] = (float)ut[s];
+    }
+  }
+}
+
 // ---- launchers ------------------------------------------------------------------
 #define ISR_FAST_ORDERS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
+
+template <int PREC>
+hipError_t launch_decompW_prec(const Job& j, int gx, hipStream_t s, void* out, int out_fp64) {
+  switch (j.order) {
+#define CASE(NN)                                                                       \
+  case NN:                                                                             \
+    hipLaunchKernelGGL((k_decompW<NN, PREC>), dim3(gx), dim3(256), 0, s, j, out, out_fp64); \
+    break;
+    ISR_FAST_ORDERS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 template <int PREC>
 hipError_t launch_fast_prec(int kind, const Job& j, int gx, hipStream_t s) {

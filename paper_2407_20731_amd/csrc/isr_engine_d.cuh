@@ -577,7 +577,72 @@ __global__ __launch_bounds__(256, dense_minb_b<N>()) void k_passBD(Job j) {
   passBD_body<N, PREC, T>(j, blockIdx.y, blockIdx.x, gridDim.x, L, false);
 }
 
+// ---- decompress of blobs made by this engine --------------------------------------
+// Kept values back into the dense slots (a tile's kept values are contiguous
+// in the blob in dense order), zeros elsewhere, and pass B's inverse on the
+// same buffer: the reconstruction pass B measured, bit for bit.
+template <int N, int PREC, int T>
+__global__ __launch_bounds__(256) void k_decompD(Job j, void* out, int out_fp64) {
+  typedef EngD<N, PREC, T> G;
+  constexpr int n3 = G::n3, S = G::S, W = G::W;
+  __shared__ float bufs[4][G::LDSW];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  typename G::Mats mt;
+  G::init(mt, j.tab, lane);
+  float* buf = bufs[wv];
+  const u64 lt = (1ull << lane) - 1ull;
+  const long long E = j.n_elem, tiles = (E + T - 1) / T, total = tiles * j.ncomp;
+  for (long long tk = (long long)blockIdx.x * 4 + wv; tk < total; tk += (long long)gridDim.x * 4) {
+    const int comp = (int)(tk / tiles);
+    const long long e0 = (tk % tiles) * T;
+    const int ne = (int)((E - e0) < T ? (E - e0) : T), nv = ne * n3;
+    const u64* gbm = j.bitmap + (size_t)comp * E * W;
+    const u64 base = j.voff[comp] + j.elem_ptr[(size_t)comp * (E + 1) + e0];
+    u32 cum = 0u;
+#pragma unroll 2
+    for (int s = 0; s < S; ++s) {
+      const int v = 64 * s + lane;
+      int e, f;
+      dense_ef<G>(v, e, f);
+      const bool keep = v < nv && ((gbm[(size_t)(e0 + e) * W + (f >> 6)] >> (f & 63)) & 1ull);
+      const u64 bk = ballot(keep);
+      float val = 0.0f;
+      if (keep) {
+        const u64 pos = base + cum + (u64)__popcll(bk & lt);
+        val = j.vbytes == 8 ? (float)((const double*)j.values)[pos] : ((const float*)j.values)[pos];
+      }
+      buf[v] = val;
+      cum += (u32)__popcll(bk);
+    }
+    asm volatile("" ::: "memory");
+    G::inverse(buf, mt, lane);
+    const size_t ob = ((size_t)comp * E + e0) * n3;
+#pragma unroll 2
+    for (int s = 0; s < S; ++s) {
+      const int v = 64 * s + lane;
+      if (v >= nv) continue;
+      if (out_fp64)
+        ((double*)out)[ob + v] = (double)buf[v];
+      else
+        ((float*)out)[ob + v] = buf[v];
+    }
+    asm volatile("" ::: "memory");
+  }
+}
+
 // ---- launchers ------------------------------------------------------------------
+template <int PREC>
+hipError_t launch_decompD_prec(const Job& j, int gx, hipStream_t s, void* out, int out_fp64) {
+#define CASE(O, T)                                                                       \
+  if (j.order == O && j.tile == T) {                                                     \
+    hipLaunchKernelGGL((k_decompD<O, PREC, T>), dim3(gx), dim3(256), 0, s, j, out, out_fp64); \
+    return hipGetLastError();                                                            \
+  }
+  ISR_DENSE_SHAPES(CASE)
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
 template <int PREC>
 hipError_t launch_dense_prec(int kind, const Job& j, int gx, hipStream_t s) {
   const dim3 grid(gx, j.ncomp), blk(256);

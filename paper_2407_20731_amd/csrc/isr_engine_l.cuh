@@ -140,6 +140,7 @@ struct SampleLdsL {
   float hs[SBINS];  // sums of energy / 2^(bin exponent), each term in [1, 2)
   double u2[4];
   int maxe;
+  int last;
 };
 
 // Forward transform of element e (field tile at `tile`) into buf; the norm
@@ -165,12 +166,10 @@ DEV void fwd_l(const double* tile, float* buf, const typename G::Mats& mt, int l
 }
 
 template <int N, int PREC>
-__global__ __launch_bounds__(256, 2) void k_sampleL(Job j) {
+DEV void sampleL_body(const Job& j, int comp, int vb, int nvb, SampleLdsL<N, PREC>& L, bool tail) {
   typedef EngL<N, PREC> G;
   constexpr int n2 = G::n2, n3 = G::n3;
-  __shared__ SampleLdsL<N, PREC> L;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int comp = blockIdx.y;
   CompState* st = j.st + comp;
   for (int k = tid; k < SBINS; k += 256) {
     L.hc[k] = 0u;
@@ -185,11 +184,11 @@ __global__ __launch_bounds__(256, 2) void k_sampleL(Job j) {
   const long long ss = j.sample_stride > 0 ? j.sample_stride : 1;
   const long long stiles = (E + ss - 1) / ss;
   const double* ub = j.u + (size_t)comp * j.comp_stride;
-  const long long nw = (long long)gridDim.x * 4;
+  const long long nw = (long long)nvb * 4;
   double u2 = 0.0;
   int maxe = 0;
   float* buf = L.buf[wv];
-  for (long long k = (long long)blockIdx.x * 4 + wv; k < stiles; k += nw) {
+  for (long long k = (long long)vb * 4 + wv; k < stiles; k += nw) {
     const long long e = k * ss;
     const double jac = j.jac ? j.jac[e] : 1.0;
     fwd_l<G>(ub + e * n3, buf, mt, lane, [&](int q, double x) {
@@ -238,6 +237,14 @@ __global__ __launch_bounds__(256, 2) void k_sampleL(Job j) {
     atomicAdd(&st->samp_u2, L.u2[0] + L.u2[1] + L.u2[2] + L.u2[3]);
     atomicMax(&st->samp_maxe, L.maxe);
   }
+  if (!tail || !last_block(j.done + D_SAMPLE * 8 + comp, &L.last, nvb)) return;
+  if (tid < 64) select_sample_body(j, comp);
+}
+
+template <int N, int PREC>
+__global__ __launch_bounds__(256, 2) void k_sampleL(Job j) {
+  __shared__ SampleLdsL<N, PREC> L;
+  sampleL_body<N, PREC>(j, blockIdx.y, blockIdx.x, gridDim.x, L, false);
 }
 
 template <int N, int PREC>
@@ -250,12 +257,10 @@ struct PassALdsL {
 };
 
 template <int N, int PREC>
-__global__ __launch_bounds__(256, 2) void k_passAL(Job j) {
+DEV void passAL_body(const Job& j, int comp, int vb, int nvb, PassALdsL<N, PREC>& L) {
   typedef EngL<N, PREC> G;
   constexpr int n2 = G::n2, n3 = G::n3;
-  __shared__ PassALdsL<N, PREC> L;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int comp = blockIdx.y;
   CompState* st = j.st + comp;
   if (st->flags & ST_MISS) return;
   const int wlo = st->win_lo, whi = st->win_hi;
@@ -276,9 +281,9 @@ __global__ __launch_bounds__(256, 2) void k_passAL(Job j) {
   u64 hi_tot = 0ull;
   u32 ncap = 0u;
   const double* ub = j.u + (size_t)comp * j.comp_stride;
-  const long long nw = (long long)gridDim.x * 4;
+  const long long nw = (long long)nvb * 4;
   float* buf = L.buf[wv];
-  for (long long e = (long long)blockIdx.x * 4 + wv; e < E; e += nw) {
+  for (long long e = (long long)vb * 4 + wv; e < E; e += nw) {
     const double jac = j.jac ? j.jac[e] : 1.0;
     fwd_l<G>(ub + e * n3, buf, mt, lane, [&](int q, double x) {
       double r;
@@ -339,7 +344,13 @@ __global__ __launch_bounds__(256, 2) void k_passAL(Job j) {
   v[5] = ke[2];
   v[6] = lane == 0 ? (long long)hi_tot : 0ll;
   block_sum_i64<7>(v, L.red, tid);
-  if (tid < 7) j.slotsA[((size_t)comp * j.gA + blockIdx.x) * 8 + tid] = L.red[0][tid];
+  if (tid < 7) j.slotsA[((size_t)comp * j.gA + vb) * 8 + tid] = L.red[0][tid];
+}
+
+template <int N, int PREC>
+__global__ __launch_bounds__(256, 2) void k_passAL(Job j) {
+  __shared__ PassALdsL<N, PREC> L;
+  passAL_body<N, PREC>(j, blockIdx.y, blockIdx.x, gridDim.x, L);
 }
 
 template <int N, int PREC>
@@ -350,15 +361,15 @@ struct PassBLdsL {
   u32 wp[4][EngL<N, PREC>::W];
   TabLdsL<EngL<N, PREC>::n3> tab;
   long long red[4][8];
+  __int128 r3[4][3];
+  int last;
 };
 
 template <int N, int PREC>
-__global__ __launch_bounds__(256, 2) void k_passBL(Job j) {
+DEV void passBL_body(const Job& j, int comp, int vb, int nvb, PassBLdsL<N, PREC>& L, bool tail) {
   typedef EngL<N, PREC> G;
   constexpr int n2 = G::n2, n3 = G::n3, W = G::W;
-  __shared__ PassBLdsL<N, PREC> L;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int comp = blockIdx.y;
   CompState* st = j.st + comp;
   if (st->flags & ST_MISS) return;
   const XParm PR = xparm(st->xm_err, j.xh);
@@ -378,12 +389,12 @@ __global__ __launch_bounds__(256, 2) void k_passBL(Job j) {
   double pr = 0.0;  // fixed-order sum of the error terms
   bool bad = false;
   const double* ub = j.u + (size_t)comp * j.comp_stride;
-  const long long nw = (long long)gridDim.x * 4;
+  const long long nw = (long long)nvb * 4;
   float* buf = L.buf[wv];
   float* cst = L.cst[wv];
   u64* bm = L.bm[wv];
   u32* wp = L.wp[wv];
-  for (long long e = (long long)blockIdx.x * 4 + wv; e < E; e += nw) {
+  for (long long e = (long long)vb * 4 + wv; e < E; e += nw) {
     const double jac = j.jac ? j.jac[e] : 1.0;
     const double* tile = ub + e * n3;
     fwd_l<G>(tile, buf, mt, lane, [](int, double) {});
@@ -486,10 +497,105 @@ __global__ __launch_bounds__(256, 2) void k_passBL(Job j) {
   long long v[3];
   xints(ar, PR, v);
   block_sum_i64<3>(v, L.red, tid);
-  if (tid < 3) j.slotsB[((size_t)comp * j.gB + blockIdx.x) * 4 + tid] = L.red[0][tid];
+  if (tid < 3) j.slotsB[((size_t)comp * j.gB + vb) * 4 + tid] = L.red[0][tid];
+  if (!tail || !last_block(j.done + D_PASSB * 8 + comp, &L.last, nvb)) return;
+  passB_tail(j, comp, L.r3);
+}
+
+template <int N, int PREC>
+__global__ __launch_bounds__(256, 2) void k_passBL(Job j) {
+  __shared__ PassBLdsL<N, PREC> L;
+  passBL_body<N, PREC>(j, blockIdx.y, blockIdx.x, gridDim.x, L, false);
+}
+
+// ---- decompress of blobs made by this engine --------------------------------------
+// Kept values into pass B's first inverse stage (the same blocks, slots and
+// in-place LDS positions), then its remaining stages: the reconstruction pass
+// B measured, bit for bit.  One element per wavefront.
+template <int N, int PREC>
+__global__ __launch_bounds__(256, 2) void k_decompL(Job j, void* out, int out_fp64) {
+  typedef EngL<N, PREC> G;
+  constexpr int n = G::n, n2 = G::n2, n3 = G::n3, W = G::W;
+  __shared__ float bufs[4][G::LDSW];
+  __shared__ u64 bms[4][W];
+  __shared__ u32 wps[4][W];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  typename G::Mats mt;
+  G::init(mt, j.tab, lane);
+  float* buf = bufs[wv];
+  u64* bm = bms[wv];
+  u32* wp = wps[wv];
+  const long long E = j.n_elem, total = E * j.ncomp;
+  for (long long tk = (long long)blockIdx.x * 4 + wv; tk < total; tk += (long long)gridDim.x * 4) {
+    const int comp = (int)(tk / E);
+    const long long e = tk % E;
+    const u64* gbm = j.bitmap + ((size_t)comp * E + e) * W;
+    const u64 base = j.voff[comp] + j.elem_ptr[(size_t)comp * (E + 1) + e];
+    for (int w = lane; w < W; w += 64) bm[w] = gbm[w];
+    asm volatile("" ::: "memory");
+    if (lane == 0) {
+      u32 run = 0u;
+      for (int w = 0; w < W; ++w) {
+        wp[w] = run;
+        run += (u32)__popcll(bm[w]);
+      }
+    }
+    asm volatile("" ::: "memory");
+#pragma unroll 1
+    for (int b = 0; b < G::NB; ++b) {
+      float cm[4], y[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        cm[m] = 0.0f;
+        if (!G::valid(b, m, lane)) continue;
+        const int f = G::axis(m, lane) * n2 + G::pencil(b, lane), w = f >> 6;
+        const u64 wd = bm[w];
+        if ((wd >> (f & 63)) & 1ull) {
+          const u64 pos = base + wp[w] + (u64)__popcll(wd & ((1ull << (f & 63)) - 1ull));
+          cm[m] = j.vbytes == 8 ? (float)((const double*)j.values)[pos] : ((const float*)j.values)[pos];
+        }
+      }
+      G::mfma(cm, y, mt.fv, mt.hv, mt.lv);
+      G::template wr<3>(buf, b, y, lane);
+    }
+    asm volatile("" ::: "memory");
+    G::template stage<2>(buf, mt.fv, mt.hv, mt.lv, lane);
+    const size_t ob = ((size_t)comp * E + e) * n3;
+#pragma unroll 1
+    for (int b = 0; b < G::NB; ++b) {
+      float x[4], y[4];
+      G::template rd<1>(buf, b, x, lane);
+      G::mfma(x, y, mt.fv, mt.hv, mt.lv);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        if (!G::valid(b, m, lane)) continue;
+        const size_t o = ob + (size_t)G::pencil(b, lane) * n + G::axis(m, lane);
+        if (out_fp64)
+          ((double*)out)[o] = (double)y[m];
+        else
+          ((float*)out)[o] = y[m];
+      }
+    }
+    asm volatile("" ::: "memory");
+  }
 }
 
 #define ISR_FAST_ORDERS_L(X) X(8) X(9) X(10) X(11)
+
+template <int PREC>
+hipError_t launch_decompL_prec(const Job& j, int gx, hipStream_t s, void* out, int out_fp64) {
+  switch (j.order) {
+#define CASE(NN)                                                                             \
+  case NN:                                                                                   \
+    hipLaunchKernelGGL((k_decompL<NN, PREC>), dim3(gx), dim3(256), 0, s, j, out, out_fp64); \
+    break;
+    ISR_FAST_ORDERS_L(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 template <int PREC>
 hipError_t launch_fast_l(int kind, const Job& j, int gx, hipStream_t s) {

@@ -1,5 +1,6 @@
 // One persistent launch over a batch of FP32 / BF16 snapshots (orders 5, 7, 9,
-// uneven sizes) on the streaming path.
+// uneven sizes, each with the tile shape its context holds for it: built-in
+// or autotuned) on the streaming path.
 //
 // The queue is phase-major, like the FP64 batch kernel's (isr_batch.cuh):
 //   sample, pass A, gather + level-1 select, refinement levels 2..6, counts,
@@ -74,7 +75,10 @@ DEV Job fb_job(const Job* jr) {
 }
 DEV int fb_u(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Bodies of one order in the persistent kernel (its tile shape: fbatch_tile).
+// Bodies of one (order, tile shape) in the persistent kernel: the dense-tile
+// engine (T > 0), the wave-tile engine (T = 0, orders up to 7) or the
+// large-order engine (T = 0, orders 8..11).  Every shape the autotuner may
+// pick for orders 5, 7 and 9 is here (ISR_FBATCH_SHAPES).
 template <int N, int PREC, int T>
 struct FbOrder {
   typedef SampleLdsD<N, PREC, T> LS;
@@ -85,7 +89,7 @@ struct FbOrder {
   static DEV void passB(const Job& j, int c, int k, int nk) { passBD_body<N, PREC, T>(j, c, k, nk, *(LB*)fb_lds, true); }
 };
 template <int N, int PREC>
-struct FbOrder<N, PREC, 0> {
+struct FbWave {
   typedef SampleLds<N, PREC> LS;
   typedef PassALds<N, PREC> LA;
   typedef PassBLds<N, PREC> LB;
@@ -93,13 +97,23 @@ struct FbOrder<N, PREC, 0> {
   static DEV void passA(const Job& j, int c, int k, int nk) { passA_body<N, PREC>(j, c, k, nk, *(LA*)fb_lds); }
   static DEV void passB(const Job& j, int c, int k, int nk) { passB_body<N, PREC>(j, c, k, nk, *(LB*)fb_lds, true); }
 };
-
-template <int PREC>
-using Fb5 = FbOrder<5, PREC, 4>;
-template <int PREC>
-using Fb7 = FbOrder<7, PREC, 0>;
-template <int PREC>
-using Fb9 = FbOrder<9, PREC, 1>;
+template <int N, int PREC>
+struct FbLarge {
+  typedef SampleLdsL<N, PREC> LS;
+  typedef PassALdsL<N, PREC> LA;
+  typedef PassBLdsL<N, PREC> LB;
+  static DEV void sample(const Job& j, int c, int k, int nk) { sampleL_body<N, PREC>(j, c, k, nk, *(LS*)fb_lds, true); }
+  static DEV void passA(const Job& j, int c, int k, int nk) { passAL_body<N, PREC>(j, c, k, nk, *(LA*)fb_lds); }
+  static DEV void passB(const Job& j, int c, int k, int nk) { passBL_body<N, PREC>(j, c, k, nk, *(LB*)fb_lds, true); }
+};
+template <int N, int PREC, int T>
+struct FbSel {
+  typedef FbOrder<N, PREC, T> type;
+};
+template <int N, int PREC>
+struct FbSel<N, PREC, 0> {
+  typedef typename Pick<(N <= FAST_MAX_ORDER), FbWave<N, PREC>, FbLarge<N, PREC>>::type type;
+};
 
 // Each body is its own (not inlined) function: the registers of one phase do
 // not constrain another's, and the kernel needs the largest of them only.
@@ -195,12 +209,15 @@ __global__ __launch_bounds__(256, 3) void k_fbatch(BatchCtl B) {
     __syncthreads();
     if (ok_s) {
       if (ph == FQ_SAMPLE || ph == FQ_PASSA || ph == FQ_PASSB) {
-        if (j.order == 5)
-          fb_engine<Fb5<PREC>>(ph, jp, comp, k, nk);
-        else if (j.order == 7)
-          fb_engine<Fb7<PREC>>(ph, jp, comp, k, nk);
-        else
-          fb_engine<Fb9<PREC>>(ph, jp, comp, k, nk);
+        const int o = j.order, t = j.tile;
+#define FB_CASE(O, T)                                                 \
+  if (o == O && t == T) {                                             \
+    fb_engine<typename FbSel<O, PREC, T>::type>(ph, jp, comp, k, nk); \
+  } else
+        ISR_FBATCH_SHAPES(FB_CASE) {
+          if (tid == 0) atomicOr(B.err, 2);  // a shape the host never enqueues
+        }
+#undef FB_CASE
       } else if (ph == FQ_GATHER) {
         fb_gather(jp, comp, k, nk);
       } else if (ph == FQ_COUNT) {
@@ -231,20 +248,26 @@ constexpr size_t fb_max(size_t m) {
   return m > sizeof(T) ? m : sizeof(T);
 }
 
+// Dynamic LDS of the persistent kernel: order 0 gives the order-independent
+// phases' share, (order, tile) that shape's bodies'; a batch launches with the
+// largest over the shapes it holds.
 template <int PREC>
-size_t fbatch_lds_prec() {
-  size_t m = sizeof(GatherLds);
-  m = fb_max<RefselLds>(m);
-  m = fb_max<ScanLds>(m);
-  m = fb_max<typename Fb5<PREC>::LS>(m);
-  m = fb_max<typename Fb5<PREC>::LA>(m);
-  m = fb_max<typename Fb5<PREC>::LB>(m);
-  m = fb_max<typename Fb7<PREC>::LS>(m);
-  m = fb_max<typename Fb7<PREC>::LA>(m);
-  m = fb_max<typename Fb7<PREC>::LB>(m);
-  m = fb_max<typename Fb9<PREC>::LS>(m);
-  m = fb_max<typename Fb9<PREC>::LA>(m);
-  m = fb_max<typename Fb9<PREC>::LB>(m);
+size_t fbatch_lds_prec(int order, int tile) {
+  size_t m = 0;
+  if (order == 0) {
+    m = sizeof(GatherLds);
+    m = fb_max<RefselLds>(m);
+    m = fb_max<ScanLds>(m);
+  }
+#define FB_LDS(O, T)                                   \
+  if (order == O && tile == T) {                       \
+    typedef typename FbSel<O, PREC, T>::type F;        \
+    m = fb_max<typename F::LS>(m);                     \
+    m = fb_max<typename F::LA>(m);                     \
+    m = fb_max<typename F::LB>(m);                     \
+  }
+  ISR_FBATCH_SHAPES(FB_LDS)
+#undef FB_LDS
   return (m + 255) & ~size_t(255);
 }
 

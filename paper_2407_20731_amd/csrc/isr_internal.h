@@ -253,6 +253,14 @@ hipError_t launch_fast_bf16(int kind, const Job& j, int grid_x, hipStream_t s);
 int resident_fast_fp64(int kind, int order);
 int resident_fast_fp32(int kind, int order);
 int resident_fast_bf16(int kind, int order);
+// Decompression of FP32 / BF16 blobs with the inverse of the engine that made
+// them (the reconstruction pass B measured): wave-tile or large-order engine
+// (tile 0, by order), or dense-tile engine (j.tile).
+enum BlobEngine { ENG_GENERAL = 0, ENG_WAVE = 1, ENG_DENSE = 2 };
+hipError_t launch_decomp_wave_fp32(const Job& j, int gx, hipStream_t s, void* out, int out_fp64);
+hipError_t launch_decomp_wave_bf16(const Job& j, int gx, hipStream_t s, void* out, int out_fp64);
+hipError_t launch_decomp_dense_fp32(const Job& j, int gx, hipStream_t s, void* out, int out_fp64);
+hipError_t launch_decomp_dense_bf16(const Job& j, int gx, hipStream_t s, void* out, int out_fp64);
 hipError_t launch_gather(const Job& j, int grid_x, hipStream_t s);
 hipError_t launch_count(const Job& j, int grid_x, hipStream_t s);
 constexpr int SCAN_CHUNK = 1024;  // elements per chunk of the element-offset scan
@@ -262,28 +270,35 @@ inline int scan_grid_elems(long long n_elem) {  // its workgroups per component
 }
 
 // Persistent batch launch of the streaming path (isr_fbatch.cuh, FP32 and
-// BF16): its phases, in queue order, and the tile shape it holds per order
-// (orders 5, 7, 9; -1: not in the persistent kernel).
+// BF16): its phases, in queue order, and the (order, tile) shapes it holds:
+// every candidate of the autotuner for orders 5, 7 and 9.
 enum FastBatchPhase {
   FQ_SAMPLE = 0, FQ_PASSA, FQ_GATHER, FQ_R2, FQ_R3, FQ_R4, FQ_R5, FQ_R6, FQ_COUNT, FQ_SCAN1, FQ_SCAN2, FQ_PASSB, NFQ
 };
 static_assert(NFQ <= NPH, "phase offsets of BatchCtl");
-inline int fbatch_tile(int order) { return order == 5 ? 4 : order == 7 ? 0 : order == 9 ? 1 : -1; }
+#define ISR_FBATCH_SHAPES(X) X(5, 0) X(5, 2) X(5, 4) X(5, 8) X(7, 0) X(7, 1) X(7, 2) X(9, 0) X(9, 1) X(9, 2)
+inline bool fbatch_shape(int order, int tile) {
+#define ISR_FB_IS(O, T) \
+  if (order == O && tile == T) return true;
+  ISR_FBATCH_SHAPES(ISR_FB_IS)
+#undef ISR_FB_IS
+  return false;
+}
 constexpr int FBATCH_MIN = 8;  // smallest FP32 / BF16 batch that takes the persistent launch
 hipError_t launch_fbatch(int precision, const BatchCtl& B, int grid, size_t lds_bytes, hipStream_t s);
-size_t fbatch_lds(int precision);
+size_t fbatch_lds(int precision, int order, int tile);
 int fbatch_resident(int precision, size_t lds_bytes);
 hipError_t launch_fbatch_fp32(const BatchCtl& B, int grid, size_t lds, hipStream_t s);
 hipError_t launch_fbatch_bf16(const BatchCtl& B, int grid, size_t lds, hipStream_t s);
-size_t fbatch_lds_fp32();
-size_t fbatch_lds_bf16();
+size_t fbatch_lds_fp32(int order, int tile);
+size_t fbatch_lds_bf16(int order, int tile);
 int fbatch_resident_fp32(size_t lds);
 int fbatch_resident_bf16(size_t lds);
 
 // Allocation-free entry point (isr_noalloc.hip): header bytes of a
-// serialized blob (48 + 64 per component) written by a kernel, and the
+// serialized blob (56 + 64 per component) written by a kernel, and the
 // per-device lookup of the fixed scratch array's address.
-constexpr int ISR_NOALLOC_HDR_MAX = 48 + 64 * 8;
+constexpr int ISR_NOALLOC_HDR_MAX = 56 + 64 * 8;
 hipError_t launch_put_bytes(const void* src, int n, void* dst, hipStream_t s);
 int noalloc_init(int device);
 

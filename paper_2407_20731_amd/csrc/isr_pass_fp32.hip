@@ -26,6 +26,11 @@ hipError_t launch_fast_fp32(int kind, const Job& j, int gx, hipStream_t s) {
   return launch_fast_prec<P_FP32>(kind, j, gx, s);
 }
 
+hipError_t launch_decomp_wave_fp32(const Job& j, int gx, hipStream_t s, void* out, int out_fp64) {
+  if (j.order > FAST_MAX_ORDER) return launch_decompL_prec<P_FP32>(j, gx, s, out, out_fp64);
+  return launch_decompW_prec<P_FP32>(j, gx, s, out, out_fp64);
+}
+
 int resident_fast_fp32(int kind, int order) {
   return order > FAST_MAX_ORDER ? resident_fast_l<P_FP32>(kind, order) : resident_fast_prec<P_FP32>(kind, order);
 }

@@ -163,7 +163,10 @@ template <int N, int PREC>
 struct XfM {
   typedef Shape<N> S;
   static constexpr int n = S::n, n2 = S::n2, n3 = S::n3, EPI = S::EPI;
-  static constexpr int KS = (n + 3) / 4;  // K steps of the FP32 instruction
+  // K steps of the FP32 instruction: step s, lane group g contracts index
+  // 4 g + s (every 16-column engine of the streaming path orders its FP32
+  // products this way, so coefficients agree with theirs bit for bit)
+  static constexpr int KS = 4;
   static constexpr int GROUPS = (EPI * n2 + 15) / 16;
   static_assert(n <= 16, "one 16-column tile per contraction");
   typedef float work_t;
@@ -179,7 +182,7 @@ struct XfM {
     const int col = lane % 16;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      const int k = 4 * s + lane / 16;
+      const int k = 4 * (lane / 16) + s;
       fr.f[s] = (col < n && k < n) ? M[col * n + k] : 0.0f;
     }
 #pragma unroll
@@ -210,7 +213,7 @@ struct XfM {
       if (PREC == P_FP32) {
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-          const int k = 4 * s + lane / 16;
+          const int k = 4 * (lane / 16) + s;
           const float x = (valid && k < n) ? (float)src[base + k * si] : 0.0f;
           d = __builtin_amdgcn_mfma_f32_16x16x4f32(x, fr.f[s], d, 0, 0, 0);
         }
@@ -711,13 +714,19 @@ __global__ __launch_bounds__(Shape<N>::THREADS) void k_pass3(Job j) {
   if (cur >= 0) lh_flush(L.hR, j.histR + (size_t)cur * HBINS, tid, T);
 }
 
-// ---- decompress (FP64 fixed-order inverse) ------------------------------------
-template <int N>
+// ---- decompress ------------------------------------------------------------------
+// The inverse of the blob's kept values with the transform of its precision:
+// FP64 blobs with the fixed-order FP64 inverse (the oracle's); FP32 / BF16
+// blobs compressed on these general passes with the same MFMA inverse as
+// pass 3, so that the reconstruction is the one whose error the compression
+// measured, bit for bit (each pencil's result depends only on its own
+// values, not on the tile it shares an instruction with).
+template <int N, int PREC>
 __global__ __launch_bounds__(Shape<N>::THREADS) void k_decompress(Job j, void* out, int out_fp64) {
   typedef Shape<N> S;
-  typedef Xf64<N> X;
+  typedef typename XfSel<N, PREC>::type X;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, EPI = S::EPI, T = S::THREADS, W = S::W;
-  __shared__ double sw[S::TILE];
+  __shared__ typename X::work_t sw[S::TILE];
   __shared__ typename X::Smem sm;
   __shared__ u64 bm[EPI * W];
   typename X::Regs rg;
@@ -758,20 +767,15 @@ __global__ __launch_bounds__(Shape<N>::THREADS) void k_decompress(Job j, void* o
       }
     }
     X::inverse(sw, sm, rg, el, a, b, act, ne, cm, ut);
-    __syncthreads();
     if (act) {
-      double* pout = sw + el * n3 + (a * n + b) * n;
+      const size_t o = ((size_t)comp * E + e0 + el) * n3 + (size_t)(a * n + b) * n;
+      if (out_fp64) {
 #pragma unroll
-      for (int i = 0; i < n; ++i) pout[i] = ut[i];
-    }
-    __syncthreads();
-    const size_t obase = ((size_t)comp * E + e0) * n3;
-    if (out_fp64) {
-      double* o = (double*)out + obase;
-      for (int k = tid; k < ne * n3; k += T) o[k] = sw[k];
-    } else {
-      float* o = (float*)out + obase;
-      for (int k = tid; k < ne * n3; k += T) o[k] = (float)sw[k];
+        for (int i = 0; i < n; ++i) ((double*)out)[o + i] = ut[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < n; ++i) ((float*)out)[o + i] = (float)ut[i];
+      }
     }
   }
 }
@@ -844,8 +848,8 @@ hipError_t launch_pass_prec(int kind, const Job& j, int grid, hipStream_t s, voi
       hipLaunchKernelGGL((k_pass3<NN, PREC>), dim3(grid), blk, 0, s, j);                                          \
     else if (kind == K_FORWARD)                                                                                   \
       hipLaunchKernelGGL((k_forward<NN, PREC>), dim3(grid), blk, 0, s, j, extra);                                 \
-    else if (kind == K_DECOMP && PREC == P_FP64)                                                                  \
-      hipLaunchKernelGGL((k_decompress<NN>), dim3(grid), blk, 0, s, j, extra, extra_i);                           \
+    else if (kind == K_DECOMP)                                                                                    \
+      hipLaunchKernelGGL((k_decompress<NN, PREC>), dim3(grid), blk, 0, s, j, extra, extra_i);                     \
     else                                                                                                          \
       return hipErrorInvalidValue;                                                                                \
     break;                                                                                                        \

@@ -209,6 +209,7 @@ struct isr_blob {
   void* dev = nullptr;  // [voff area 256 B][bitmap][elem_ptr][values]
   size_t dev_bytes = 0;
   int order = 0, ncomp = 0, vbytes = 8, W = 0, precision = 0, status = 0;
+  int engine = 0, tile = 0;  // FP32 / BF16: the engine (and dense tile) whose inverse decompresses it
   int64_t n_elem = 0;
   double tol = 0;
   struct Hdr {
@@ -223,7 +224,7 @@ struct isr_blob {
   size_t ptr_bytes() const { return (size_t)ncomp * (n_elem + 1) * 8; }
   void* values() const { return (char*)elem_ptr() + ptr_bytes(); }
   size_t values_bytes() const { return (size_t)total_kept * vbytes; }
-  static constexpr size_t HDR = 48, CHDR = 64;
+  static constexpr size_t HDR = 56, CHDR = 64;
   size_t serialized() const { return HDR + CHDR * ncomp + bitmap_bytes() + ptr_bytes() + values_bytes(); }
 };
 
@@ -307,6 +308,7 @@ static int check_field(const isr_field* f) {
     return fail(ISR_EINVAL, "unknown precision %d", f->precision);
   if (f->comp_stride < 0 || (f->comp_stride > 0 && f->comp_stride < f->n_elem * n3))
     return fail(ISR_EINVAL, "comp_stride smaller than one component");
+  if (f->flags & ~ISR_FIELD_COPY) return fail(ISR_EINVAL, "unknown field flags 0x%x", f->flags);
   return ISR_OK;
 }
 
@@ -369,6 +371,15 @@ struct BlobPtrs {
 };
 
 static BlobPtrs blob_ptrs(const isr_blob* b) { return {b->voff(), b->bitmap(), b->elem_ptr(), b->values()}; }
+
+// Record which engine's inverse reproduces the reconstruction that pass B
+// measured (FP32 / BF16 blobs; FP64 blobs always use the fixed-order FP64
+// inverse): the streaming path's wave-tile / large-order engine (tile 0) or
+// dense-tile engine, else the general passes.
+static void set_engine(isr_blob* b, bool fast, int tile) {
+  b->engine = b->precision == ISR_PREC_FP64 || !fast ? ENG_GENERAL : (tile > 0 ? ENG_DENSE : ENG_WAVE);
+  b->tile = b->engine == ENG_DENSE ? tile : 0;
+}
 
 static Job make_job(isr_ctx* c, const isr_field* f, const Sizes& z, char* scratch, const BlobPtrs& bp) {
   Job j;
@@ -603,6 +614,7 @@ static void fill_stats(isr_blob* b, const CompState* hs, isr_stats* st) {
 namespace isr {
 
 int ctx_device(const isr_ctx* c) { return c->device; }
+Arena* ctx_arena(isr_ctx* c) { return c->arena.get(); }
 int ctx_max_inflight(const isr_ctx* c) { return c->max_inflight; }
 uint64_t ctx_budget(const isr_ctx* c) { return c->arena->budget(); }
 
@@ -801,6 +813,7 @@ int task_step(Task* t, isr_blob** out) {
   t->st.phase_ms[6] = t->repair_ms;
   t->st.repair_iters = t->iters;
   t->st.path = t->fast ? 1 : 0;
+  set_engine(b, t->fast, t->z.tile);
   t->st.status = b->status;
   t->st.t_start = t->t_start;
   t->st.t_done = now_s();
@@ -873,7 +886,7 @@ static int run_batch_stream(isr_ctx* c, const isr_field* fs, int count, isr_blob
   for (int i = 0; i < count; ++i) {
     outs[i] = nullptr;
     Snap& x = sn[i];
-    x.z = plan_sizes(&fs[i], fbatch_tile(fs[i].order));
+    x.z = plan_sizes(&fs[i], ctx_tile(c, fs[i].order, fs[i].precision));
     x.scratch = (char*)c->arena->alloc(x.z.scratch_bytes);
     x.b = x.scratch ? new_blob(c, &fs[i], x.z) : nullptr;
     x.hs = grab_host_state(c);
@@ -968,7 +981,10 @@ static int run_batch_stream(isr_ctx* c, const isr_field* fs, int count, isr_blob
     for (int i = 0; i < count && !rc; ++i)
       if (launch_zero(sn[i].scratch, sn[i].z.zero_bytes, s) != hipSuccess) rc = fail(ISR_EDEVICE, "zero fill failed");
     if (rc) break;
-    const size_t lds = fbatch_lds(prec);
+    // LDS for the largest of the shapes this batch holds (and the
+    // order-independent phases)
+    size_t lds = fbatch_lds(prec, 0, 0);
+    for (int i = 0; i < count; ++i) lds = std::max(lds, fbatch_lds(prec, fs[i].order, sn[i].z.tile));
     const int grid = c->num_cu * fbatch_resident(prec, lds);
     if (launch_fbatch(prec, B, grid, lds, s) != hipSuccess) {
       rc = fail(ISR_EDEVICE, "batch launch failed: %s", hipGetErrorString(hipGetLastError()));
@@ -1019,6 +1035,7 @@ static int run_batch_stream(isr_ctx* c, const isr_field* fs, int count, isr_blob
       b->dev_bytes = (used + 255) & ~size_t(255);
       tmp.status = ISR_OK;
       tmp.path = 2;
+      set_engine(b, true, x.z.tile);
       tmp.t_start = t_start;
       tmp.t_done = now_s();
       if (sti) *sti = tmp;
@@ -1040,10 +1057,11 @@ int run_batch(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_s
     if ((o != 5 && o != 7 && o != 9) || p != fs[0].precision) persistent = stream = false;
     // FP64: the persistent kernel of the general passes (exact, so equal to
     // compressing alone); FP32 / BF16: the persistent kernel of the streaming
-    // passes (for the tile shapes it holds), or on request the concurrent
-    // per-snapshot pipelines
+    // passes, with each order's tile shape from the context's table (built-in
+    // or autotuned; the kernel holds every candidate), or on request the
+    // concurrent per-snapshot pipelines
     if (p != ISR_PREC_FP64) persistent = false;
-    if (p == ISR_PREC_FP64 || !stream || ctx_tile(c, o, p) != fbatch_tile(o)) stream = false;
+    if (p == ISR_PREC_FP64 || !stream || !fbatch_shape(o, ctx_tile(c, o, p))) stream = false;
   }
   // (a handful of snapshots keeps the phases of one snapshot apart in the
   // queue and leaves most workgroups waiting: their own pipelines are faster)
@@ -1456,9 +1474,27 @@ int isr_decompress(isr_ctx* c, const isr_blob* b, void* d_out, int32_t out_prec,
   j.elem_ptr = b->elem_ptr();
   j.values = b->values();
   j.voff = b->voff();
-  const long long total = (long long)tiles_per_comp(b->order, b->n_elem) * b->ncomp;
-  const int grid = (int)std::min<long long>(total, (long long)c->num_cu * 8);
-  HIPCHK(launch_pass(K_DECOMP, ISR_PREC_FP64, j, grid, (hipStream_t)stream, d_out, out_prec == ISR_PREC_FP64));
+  const int ofp64 = out_prec == ISR_PREC_FP64;
+  hipStream_t s = (hipStream_t)stream;
+  if (b->engine == ENG_GENERAL) {
+    // FP64 blobs: the fixed-order FP64 inverse; FP32 / BF16 blobs of the
+    // general passes: their MFMA inverse
+    const long long total = (long long)tiles_per_comp(b->order, b->n_elem) * b->ncomp;
+    const int grid = (int)std::min<long long>(total, (long long)c->num_cu * 8);
+    HIPCHK(launch_pass(K_DECOMP, b->vbytes == 8 ? ISR_PREC_FP64 : b->precision, j, grid, s, d_out, ofp64));
+    return ISR_OK;
+  }
+  // FP32 / BF16 blobs of the streaming engines: that engine's inverse, one
+  // tile (or element) per wavefront
+  j.tile = b->tile;
+  const long long epw = b->engine == ENG_DENSE ? b->tile : fast_epw(b->order, 0);
+  const long long waves = (b->n_elem + epw - 1) / epw * b->ncomp;
+  const int grid = (int)std::max<long long>(1, std::min<long long>((waves + 3) / 4, (long long)c->num_cu * 8));
+  const bool bf = b->precision == ISR_PREC_BF16;
+  if (b->engine == ENG_DENSE)
+    HIPCHK(bf ? launch_decomp_dense_bf16(j, grid, s, d_out, ofp64) : launch_decomp_dense_fp32(j, grid, s, d_out, ofp64));
+  else
+    HIPCHK(bf ? launch_decomp_wave_bf16(j, grid, s, d_out, ofp64) : launch_decomp_wave_fp32(j, grid, s, d_out, ofp64));
   return ISR_OK;
 }
 
@@ -1504,7 +1540,7 @@ int isr_blob_size(const isr_blob* b, uint64_t* bytes) {
 
 static void put_hdr(const isr_blob* b, char* p) {
   std::memcpy(p, "ISR1", 4);
-  uint32_t ver = 1;
+  uint32_t ver = 2;
   std::memcpy(p + 4, &ver, 4);
   int32_t v32 = b->order;
   std::memcpy(p + 8, &v32, 4);
@@ -1521,6 +1557,10 @@ static void put_hdr(const isr_blob* b, char* p) {
   std::memcpy(p + 40, &v32, 4);
   v32 = b->status;
   std::memcpy(p + 44, &v32, 4);
+  v32 = b->engine;
+  std::memcpy(p + 48, &v32, 4);
+  v32 = b->tile;
+  std::memcpy(p + 52, &v32, 4);
   for (int k = 0; k < b->ncomp; ++k) std::memcpy(p + isr_blob::HDR + isr_blob::CHDR * k, &b->comp[k], isr_blob::CHDR);
 }
 
@@ -1561,9 +1601,23 @@ int isr_blob_from_host(isr_ctx* c, const void* buf, uint64_t nbytes, isr_blob** 
   b->precision = v32;
   std::memcpy(&v32, p + 44, 4);
   b->status = v32;
+  uint32_t ver;
+  std::memcpy(&ver, p + 4, 4);
+  std::memcpy(&v32, p + 48, 4);
+  b->engine = v32;
+  std::memcpy(&v32, p + 52, 4);
+  b->tile = v32;
+  if (ver != 2) return fail(ISR_EINVAL, "blob version %u is not 2", ver);
   if (b->order < 1 || b->order > ISR_MAX_ORDER || b->ncomp < 1 || b->ncomp > ISR_MAX_COMP || b->n_elem < 1 ||
-      (b->vbytes != 4 && b->vbytes != 8) || b->W != words_per_elem(b->order))
+      (b->vbytes != 4 && b->vbytes != 8) || b->W != words_per_elem(b->order) ||
+      (b->vbytes == 8) != (b->precision == ISR_PREC_FP64) ||
+      (b->precision != ISR_PREC_FP64 && b->precision != ISR_PREC_FP32 && b->precision != ISR_PREC_BF16))
     return fail(ISR_EINVAL, "corrupt blob header");
+  if ((b->engine == ENG_GENERAL && b->tile != 0) ||
+      (b->engine == ENG_WAVE && (b->tile != 0 || !fast_order(b->order, b->precision) || b->precision == ISR_PREC_FP64)) ||
+      (b->engine == ENG_DENSE && (!dense_shape(b->order, b->tile) || b->precision == ISR_PREC_FP64)) ||
+      b->engine < ENG_GENERAL || b->engine > ENG_DENSE)
+    return fail(ISR_EINVAL, "corrupt blob header (engine %d, tile %d)", b->engine, b->tile);
   if (nbytes < isr_blob::HDR + isr_blob::CHDR * (size_t)b->ncomp) return fail(ISR_EINVAL, "truncated blob");
   uint64_t tk = 0;
   for (int k = 0; k < b->ncomp; ++k) {
@@ -1703,6 +1757,7 @@ int run_compress_noalloc(isr_ctx* c, const isr_field* f, char* scratch, size_t s
   if (f->tol >= 0.0)
     for (int k = 0; k < nc; ++k) within = within && !(hs[k].rel > f->tol);
   b.status = within ? ISR_OK : ISR_ETOL;
+  set_engine(&b, fast, z.tile);
   char hdr[isr_blob::HDR + isr_blob::CHDR * ISR_MAX_COMP];
   put_hdr(&b, hdr);
   HIPCHK(launch_put_bytes(hdr, (int)hb, d_out, s));

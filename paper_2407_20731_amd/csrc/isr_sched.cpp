@@ -48,21 +48,58 @@ Scheduler::~Scheduler() {
   for (auto& kv : reqs_) {
     if (kv.second.blob) isr_blob_free(kv.second.blob);
     if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
+    release_copy(kv.second);
   }
 }
 
+// A finished (or failed) request no longer reads its copy of the field.
+void Scheduler::release_copy(Req& r) {
+  if (r.copy) ctx_arena(ctx_)->free(r.copy);
+  r.copy = nullptr;
+}
+
 int Scheduler::submit(const isr_field* f, uint64_t* req) {
-  const uint64_t fp = request_footprint(f);
-  if (fp > ctx_budget(ctx_)) return ISR_ENOMEM;
+  const long long n = f->order + 1, n3 = n * n * n;
+  const size_t fbytes = (size_t)f->ncomp * f->n_elem * n3 * 8, jbytes = f->elem_jac ? (size_t)f->n_elem * 8 : 0;
+  const bool copy = (f->flags & ISR_FIELD_COPY) != 0;
+  const uint64_t fp = request_footprint(f) + (copy ? fbytes + jbytes + 512 : 0);
+  if (fp > ctx_budget(ctx_)) return set_error(ISR_ENOMEM, "request footprint %llu exceeds the HBM budget",
+                                              (unsigned long long)fp);
   Req r;
   r.f = *f;
   r.t_submit = now_s();
   std::memset(&r.st, 0, sizeof(r.st));
-  // the field is ready once the producer's stream reaches this point
+  hipStream_t ps = (hipStream_t)f->stream;
+  if (copy) {
+    // copy-on-submit: the field (compact, component after component) and the
+    // Jacobians into the arena, on the producer's stream, before returning
+    r.copy = ctx_arena(ctx_)->alloc(fbytes + jbytes + 256, true);
+    if (!r.copy) return set_error(ISR_ENOMEM, "the copy of the field (%zu bytes) does not fit the HBM budget now", fbytes);
+    const size_t stride = (size_t)(f->comp_stride ? f->comp_stride : f->n_elem * n3);
+    const size_t cbytes = (size_t)f->n_elem * n3 * 8;
+    double* dst = (double*)r.copy;
+    bool ok = true;
+    for (int c = 0; c < f->ncomp && ok; ++c)
+      ok = hipMemcpyAsync((char*)dst + c * cbytes, f->field + c * stride, cbytes, hipMemcpyDeviceToDevice, ps) == hipSuccess;
+    double* jac = nullptr;
+    if (ok && f->elem_jac) {
+      jac = (double*)((char*)r.copy + ((fbytes + 255) & ~size_t(255)));
+      ok = hipMemcpyAsync(jac, f->elem_jac, jbytes, hipMemcpyDeviceToDevice, ps) == hipSuccess;
+    }
+    if (!ok) {
+      ctx_arena(ctx_)->free(r.copy);
+      return set_error(ISR_EDEVICE, "copy of the field failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    r.f.field = dst;
+    r.f.comp_stride = 0;
+    r.f.elem_jac = jac;
+  }
+  // the field (or its copy) is ready once the producer's stream reaches this point
   if (hipEventCreateWithFlags(&r.ready, hipEventDisableTiming) != hipSuccess ||
-      hipEventRecord(r.ready, (hipStream_t)f->stream) != hipSuccess) {
+      hipEventRecord(r.ready, ps) != hipSuccess) {
     if (r.ready) (void)hipEventDestroy(r.ready);
-    return ISR_EDEVICE;
+    if (r.copy) ctx_arena(ctx_)->free(r.copy);
+    return set_error(ISR_EDEVICE, "event record on the producer stream failed");
   }
   {
     std::lock_guard<std::mutex> g(mu_);
@@ -100,6 +137,7 @@ bool Scheduler::admit_locked() {
     if (rc != ISR_OK) {
       r.done = true;
       r.status = rc;
+      release_copy(r);
       any = true;
       continue;
     }
@@ -137,6 +175,7 @@ void Scheduler::loop() {
       r.done = true;
       r.status = rc;
       r.blob = b;
+      release_copy(r);
       r.st = s.t.st;
       r.st.t_submit = r.t_submit;
       r.st.status = rc;

@@ -82,6 +82,7 @@ int run_compress_noalloc(isr_ctx* c, const isr_field* f, char* scratch, size_t s
 // set the calling thread's isr_last_error() text and return code
 int set_error(int code, const char* fmt, ...);
 int ctx_device(const isr_ctx* c);
+Arena* ctx_arena(isr_ctx* c);
 int ctx_max_inflight(const isr_ctx* c);
 uint64_t ctx_budget(const isr_ctx* c);
 
@@ -126,7 +127,8 @@ class Scheduler {
     uint64_t id = 0;
     isr_field f;
     double t_submit = 0;
-    hipEvent_t ready = nullptr;  // producer stream's state at submit time
+    hipEvent_t ready = nullptr;  // producer stream's state at submit time (after the copy, if any)
+    void* copy = nullptr;        // copy-on-submit: the library's copy of the field (and Jacobians)
     bool done = false;
     int status = 0;
     isr_blob* blob = nullptr;
@@ -140,6 +142,7 @@ class Scheduler {
   };
   void loop();
   bool admit_locked();
+  void release_copy(Req& r);
   isr_ctx* ctx_;
   std::mutex mu_;
   std::condition_variable cv_, done_cv_;

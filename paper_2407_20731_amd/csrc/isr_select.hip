@@ -201,7 +201,7 @@ int resident_fast(int kind, int precision, int order, int tile) {
 }
 
 hipError_t launch_pass(int kind, int precision, const Job& j, int grid, hipStream_t s, void* extra, int extra_i) {
-  if (kind == K_DECOMP || precision == ISR_PREC_FP64) return launch_pass_fp64(kind, j, grid, s, extra, extra_i);
+  if (precision == ISR_PREC_FP64) return launch_pass_fp64(kind, j, grid, s, extra, extra_i);
   if (precision == ISR_PREC_FP32) return launch_pass_fp32(kind, j, grid, s, extra, extra_i);
   if (precision == ISR_PREC_BF16) return launch_pass_bf16(kind, j, grid, s, extra, extra_i);
   return hipErrorInvalidValue;
@@ -232,7 +232,9 @@ hipError_t launch_fbatch(int precision, const BatchCtl& B, int grid, size_t lds_
   return hipErrorInvalidValue;
 }
 
-size_t fbatch_lds(int precision) { return precision == ISR_PREC_FP32 ? fbatch_lds_fp32() : fbatch_lds_bf16(); }
+size_t fbatch_lds(int precision, int order, int tile) {
+  return precision == ISR_PREC_FP32 ? fbatch_lds_fp32(order, tile) : fbatch_lds_bf16(order, tile);
+}
 
 int fbatch_resident(int precision, size_t lds_bytes) {
   return precision == ISR_PREC_FP32 ? fbatch_resident_fp32(lds_bytes) : fbatch_resident_bf16(lds_bytes);

@@ -30,6 +30,7 @@ OK, PENDING, EINVAL, ENOMEM, EDEVICE, ETOL, ECANCELED, ENOTFOUND = 0, 1, -1, -2,
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 FLAG_TIMING = 1
 FLAG_BATCH_STREAMS = 2  # FP32/BF16 batches on the scheduler's streams instead of one persistent launch
+FIELD_COPY = 1  # isr_field.flags: copy-on-submit
 MAX_COMP = 8
 NPHASE = 9
 PHASES = ("pass1", "select1", "pass2", "refine", "pass3", "finalize", "repair", "fallback", "sample")
@@ -52,7 +53,7 @@ class isr_config(C.Structure):
 class isr_field(C.Structure):
     _fields_ = [("field", C.c_void_p), ("n_elem", C.c_int64), ("order", C.c_int32), ("ncomp", C.c_int32),
                 ("comp_stride", C.c_int64), ("tol", C.c_double), ("precision", C.c_int32),
-                ("reserved", C.c_int32), ("elem_jac", C.c_void_p), ("stream", C.c_void_p)]
+                ("flags", C.c_int32), ("elem_jac", C.c_void_p), ("stream", C.c_void_p)]
 
 
 class isr_tune_report(C.Structure):
@@ -161,6 +162,8 @@ class BlobArrays:
     tol: float
     precision: int
     status: int
+    engine: int                # FP32 / BF16: engine whose inverse decompresses it (0 general, 1 wave-tile, 2 dense)
+    tile: int                  # its dense tile (engine 2)
     comps: List[dict]          # U2, B, tau, dropped, err2, rel_err, kept, voff
     bitmap: np.ndarray         # uint64 [ncomp, n_elem, W]
     elem_ptr: np.ndarray       # uint64 [ncomp, n_elem + 1]
@@ -171,9 +174,12 @@ def parse_blob(buf: bytes) -> BlobArrays:
     """Split a serialized blob (layout documented in include/isr.h)."""
     if buf[:4] != b"ISR1":
         raise ValueError("not an ISR1 blob")
-    order, ncomp, n_elem, vb, W, tol, prec, status = struct.unpack_from("<iiqiidii", buf, 8)
+    version, = struct.unpack_from("<I", buf, 4)
+    if version != 2:
+        raise ValueError(f"blob version {version} is not 2")
+    order, ncomp, n_elem, vb, W, tol, prec, status, engine, tile = struct.unpack_from("<iiqiidiiii", buf, 8)
     comps = []
-    off = 48
+    off = 56
     for _ in range(ncomp):
         U2, B, tau, dropped, err2, rel, kept, voff = struct.unpack_from("<6d2Q", buf, off)
         comps.append(dict(U2=U2, B=B, tau=tau, dropped=dropped, err2=err2, rel_err=rel, kept=kept, voff=voff))
@@ -188,7 +194,7 @@ def parse_blob(buf: bytes) -> BlobArrays:
     values = []
     for c in comps:
         values.append(np.frombuffer(buf, dtype=vdt, count=c["kept"], offset=off + c["voff"] * vb))
-    return BlobArrays(order, ncomp, n_elem, vb, W, tol, prec, status, comps, bitmap, elem_ptr, values)
+    return BlobArrays(order, ncomp, n_elem, vb, W, tol, prec, status, engine, tile, comps, bitmap, elem_ptr, values)
 
 
 class Blob:
@@ -296,7 +302,7 @@ class Context:
                 raise ValueError("jac must be a contiguous float64 CUDA tensor of n_elem entries")
             jp = jac.data_ptr()
         return isr_field(field=u.data_ptr(), n_elem=n_elem or E, order=order, ncomp=ncomp,
-                         comp_stride=stride, tol=float(tol), precision=p, reserved=0,
+                         comp_stride=stride, tol=float(tol), precision=p, flags=0,
                          elem_jac=jp, stream=_stream_ptr(stream))
 
     def get_tile(self, order: int, precision) -> int:
@@ -352,8 +358,12 @@ class Context:
             _check(rc, "isr_compress_batch")
         return [Blob(self, hs[i], _stats_dict(sts[i], fs[i].ncomp), sts[i].status) for i in range(len(fields))]
 
-    def submit(self, u, order: int, tol: float, precision="fp64", stream=None) -> int:
+    def submit(self, u, order: int, tol: float, precision="fp64", stream=None, copy: bool = False) -> int:
+        """Queue a compression; with copy=True the library copies the field at
+        submit (copy-on-submit) and the caller may overwrite it at once (on
+        the same stream)."""
         f = self._field(u, order, tol, precision, None, stream)
+        f.flags = FIELD_COPY if copy else 0
         req = C.c_uint64()
         _check(load_library().isr_submit(self._h, C.byref(f), C.byref(req)), "isr_submit")
         return req.value

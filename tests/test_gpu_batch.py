@@ -1,8 +1,9 @@
 """One persistent launch over a batch of snapshots (orders 5, 7, 9, uneven
 sizes): every result must equal the same snapshot compressed alone, bit for
 bit (the global sums are exact, or fixed-order per lane with the same grids,
-so the queue order cannot change them), and the FP64 members must equal the
-oracle.  FP32 / BF16 batches run as one persistent launch of the streaming
+so the queue order cannot change them); the FP64 members must equal the
+oracle, and the FP32 / BF16 members pass the oracle checks of
+tests/mixed_checks.py.  FP32 / BF16 batches run as one persistent launch of the streaming
 path; with FLAG_BATCH_STREAMS as one streaming pipeline per snapshot on the
 scheduler's streams, with the same results."""
 
@@ -54,6 +55,28 @@ def test_batch_equals_alone(isr_ctx, prec):
                 assert same, (N, E)
 
 
+@pytest.mark.parametrize("shapes", [{5: 2, 7: 1, 9: 0}, {5: 8, 7: 2, 9: 2}, {5: 0, 7: 0, 9: 1}])
+def test_batch_persistent_takes_every_shape(shapes):
+    """The persistent launch runs whatever tile shape the context holds per
+    order (the autotuner's candidates: wave-tile, dense tiles, the large-order
+    engine), and every member equals its result alone with the same shapes."""
+    from paper_2407_20731_amd import isr
+    rng = np.random.default_rng(15)
+    snaps = _batch(rng, 9, 30, 2000, 1100)
+    torch.cuda.synchronize()
+    with isr.Context() as ctx:
+        for N, t in shapes.items():
+            ctx.set_tile(N, "bf16", t)
+        print(f"[case] batch shapes {shapes} sizes={[(N, E) for N, E, _ in snaps]}", flush=True)
+        blobs = ctx.compress_batch([(u, N, 1e-3) for N, E, u in snaps], "bf16")
+        paths = [b.stats["path"] for b in blobs]
+        assert paths.count(2) >= len(blobs) - 1, paths
+        for (N, E, u), b in zip(snaps, blobs):
+            assert b.status == 0
+            same = b.to_bytes() == ctx.compress(u, N, 1e-3, "bf16").to_bytes()
+            assert same, (N, E, shapes[N])
+
+
 def test_batch_fp64_matches_oracle(isr_ctx):
     rng = np.random.default_rng(12)
     snaps = _batch(rng, 6, 20, 400, 800)
@@ -66,6 +89,28 @@ def test_batch_fp64_matches_oracle(isr_ctx):
             assert arr.comps[c]["tau"] == rc.tau and arr.comps[c]["kept"] == rc.kept
             assert np.array_equal(arr.bitmap[c], rc.bitmap)
             assert np.array_equal(arr.values[c].view(np.uint64), rc.values.view(np.uint64))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batch_mixed_matches_oracle(isr_ctx, prec):
+    """Every member of an FP32 / BF16 batch (ten snapshots: the persistent
+    launch) against the oracle with the checks of tests/mixed_checks.py,
+    its decompressed output included."""
+    from mixed_checks import verify_mixed
+    rng = np.random.default_rng(14)
+    snaps = _batch(rng, 10, 20, 600, 1000)
+    torch.cuda.synchronize()
+    print(f"[case] batch oracle prec={prec} sizes={[(N, E) for N, E, _ in snaps]}", flush=True)
+    blobs = isr_ctx.compress_batch([(u, N, 1e-3) for N, E, u in snaps], prec)
+    assert [b.stats["path"] for b in blobs].count(2) >= len(blobs) // 2
+    for (N, E, u), b in zip(snaps, blobs):
+        assert b.status == 0
+        u_np = u.cpu().numpy()
+        coef = isr_ctx.forward(u, N, prec).cpu().numpy().astype(np.float64)
+        out = isr_ctx.decompress(b).cpu().numpy()
+        ref = oracle.compress(u_np, N, 1e-3, keep_arrays=True)
+        rep = verify_mixed(b.arrays(), b.status, b.stats["repair_iters"], u_np, N, 1e-3, prec, coef, ref.comps, out=out)
+        print(f"[batch-oracle] {prec} N={N} E={E} path={b.stats['path']}: {rep}", flush=True)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])

@@ -4,14 +4,16 @@ Requests of different sizes and orders (element windows of device-resident
 pools, FP32 MFMA path, tol 1e-3) are submitted back to back; the scheduler
 admits them while stream slots and HBM budget are free and their pipelines
 overlap on the device.  Each result must equal the same request compressed
-alone (bit-identical: every global sum is exact, so scheduling cannot change
-it), requests must actually overlap, and a small budget must bound what is
-admitted without deadlock.
+alone (bit-identical: every global sum is exact or fixed-order per lane, so
+scheduling cannot change it) and pass the oracle checks of
+tests/mixed_checks.py, requests must actually overlap, and a small budget
+must bound what is admitted without deadlock.
 """
 
 import numpy as np
 import pytest
 
+import oracle
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -47,6 +49,21 @@ def test_mix_equals_alone_and_overlaps():
             assert m.status == isr.OK and a.status == isr.OK
             assert m.to_bytes() == a.to_bytes(), (N, off, E)
             assert max(m.stats["rel_err"]) <= 1e-3
+        # the served results against the oracle (the smaller requests, to keep
+        # the CPU side short)
+        from mixed_checks import verify_mixed
+        checked = 0
+        for (N, off, E), m in zip(reqs, mixed):
+            if E > 1000 or checked >= 10:
+                continue
+            x = pools[N][:, off:off + E]
+            u_np = x.cpu().numpy()
+            coef = ctx.forward(x, N, "fp32").cpu().numpy().astype(np.float64)
+            out = ctx.decompress(m).cpu().numpy()
+            ref = oracle.compress(u_np, N, 1e-3, keep_arrays=True)
+            verify_mixed(m.arrays(), m.status, m.stats["repair_iters"], u_np, N, 1e-3, "fp32", coef, ref.comps, out=out)
+            checked += 1
+        assert checked >= 5
         spans = sorted((m.stats["t_start"], m.stats["t_done"]) for m in mixed)
         overlaps = sum(1 for k in range(1, len(spans)) if spans[k][0] < spans[k - 1][1])
         print(f"[serving] {len(spans)} requests, {overlaps} started before the previous one finished", flush=True)
@@ -102,3 +119,45 @@ def test_arena_gives_back_empty_chunks():
         b = ctx.compress(big, 7, 1e-3, "bf16")
         assert b.status == 0
         b.free()
+
+
+def test_copy_on_submit_lets_the_caller_overwrite():
+    """With copy-on-submit the caller overwrites the field on its stream right
+    after isr_submit returns, while the request still waits for a slot; the
+    result equals compressing the original field."""
+    from paper_2407_20731_amd import isr
+    u = synth.field_torch(3000, 7, ncomp=3, seed=61, device="cuda")
+    keep = u.clone()
+    big = synth.field_torch(20000, 9, ncomp=3, seed=62, device="cuda")
+    torch.cuda.synchronize()
+    with isr.Context(device=0, max_inflight=1) as ctx:
+        first = ctx.submit(big, 9, 1e-3, "bf16")  # holds the only slot for a while
+        rid = ctx.submit(u, 7, 1e-3, "bf16", copy=True)
+        u.fill_(1.0e30)  # same (current) stream: ordered after the copy
+        b = ctx.poll(rid, wait_ms=-1)
+        ctx.poll(first, wait_ms=-1).free()
+        ref = ctx.compress(keep, 7, 1e-3, "bf16")
+        assert b.status == isr.OK
+        assert b.to_bytes() == ref.to_bytes()
+        # a window with a component stride is copied compactly
+        pool = synth.field_torch(5000, 5, ncomp=3, seed=63, device="cuda")
+        win = pool[:, 1000:3000]
+        rid = ctx.submit(win, 5, 1e-3, "fp32", copy=True)
+        pool.zero_()
+        b2 = ctx.poll(rid, wait_ms=-1)
+        pool2 = synth.field_torch(5000, 5, ncomp=3, seed=63, device="cuda")
+        assert b2.to_bytes() == ctx.compress(pool2[:, 1000:3000], 5, 1e-3, "fp32").to_bytes()
+
+
+def test_copy_on_submit_counts_against_the_budget():
+    """The copy is part of the request's footprint: a request that fits the
+    budget borrowed is refused at submit when its copy would not fit too."""
+    from paper_2407_20731_amd import isr
+    u = synth.field_torch(2000, 7, ncomp=3, seed=64, device="cuda")  # ~63 MB footprint, 25 MB field
+    torch.cuda.synchronize()
+    with isr.Context(device=0, budget_bytes=75 << 20) as ctx:
+        with pytest.raises(isr.IsrError) as e:
+            ctx.submit(u, 7, 1e-3, "fp32", copy=True)
+        assert e.value.code == isr.ENOMEM
+        b = ctx.poll(ctx.submit(u, 7, 1e-3, "fp32"), wait_ms=-1)
+        assert b.status == isr.OK
