@@ -9,15 +9,21 @@ transforms, FP64 norm / threshold / check).  A step is one full compression
 timed on the plain FP64 path (speedup reported), and two more sections run:
 
   batch    32 snapshots, element counts log-uniform 4k-200k, N in {5,7,9},
-           3 FP64 components, tol 1e-3, one persistent launch
+           3 FP64 components, tol 1e-3, autotuned tile shapes: one streaming
+           pipeline per snapshot on the scheduler's streams, and the same batch
+           as one persistent launch
   serving  open-loop Poisson arrivals, element counts lognormal (median 20k,
            sigma 1, clipped 1k-500k), N in {5,7,9}, FP32 MFMA path, tol 1e-3,
-           64 GB admission budget: p50 / p99 latency and GB/s
+           64 GB admission budget: p50 / p99 latency and GB/s at 0.5, 0.7 and
+           0.9 of the saturated rate, 4 and 8 resident requests
+  hybrid   the headline snapshot's blobs coded losslessly (bzip2, zlib) on 12
+           host threads beside the GPU compressions: GPU stall, host time,
+           compression ratio of the whole chain
 
 Output: ONE JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision auto|fp64|fp32|bf16]
-                    [--no-cpu] [--no-batch] [--no-serving]
+                    [--no-cpu] [--no-batch] [--no-serving] [--no-hybrid]
 """
 
 from __future__ import annotations
@@ -238,18 +244,18 @@ def against_oracle(gpu: dict, ref, u) -> dict:
     return out
 
 
-def time_single(ctx, u, prec, steps, warmup, stream, order=ORDER):
+def time_single(ctx, u, prec, steps, warmup, stream, order=ORDER, tol=TOL):
     import numpy as np
     import torch
 
     for _ in range(warmup):
-        ctx.compress(u, order, TOL, prec, stream=stream).free()
+        ctx.compress(u, order, tol, prec, stream=stream).free()
     torch.cuda.synchronize()
     phases, rels, kept, status = {}, [], [], set()
     blob_bytes = 0
     t0 = time.perf_counter()
     for _ in range(steps):
-        b = ctx.compress(u, order, TOL, prec, stream=stream)
+        b = ctx.compress(u, order, tol, prec, stream=stream)
         for k, v in b.stats["phase_ms"].items():
             phases.setdefault(k, []).append(v)
         rels.append(max(b.stats["rel_err"]))
@@ -286,7 +292,7 @@ def run_batch(ctx, pool, prec, reps=3):
     # set (device allocations) outside the timed region
     for b in ctx.compress_batch(fields, prec):
         b.free()
-    times, ok, rel = [], True, 0.0
+    times, ok, rel, paths = [], True, 0.0, {}
     for _ in range(reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -295,64 +301,149 @@ def run_batch(ctx, pool, prec, reps=3):
         times.append(time.perf_counter() - t0)
         ok = ok and all(b.status == 0 for b in blobs)
         rel = max(rel, max(max(b.stats["rel_err"]) for b in blobs))
+        paths = {}
         for b in blobs:
+            paths[b.stats["path"]] = paths.get(b.stats["path"], 0) + 1
             b.free()
     dt = sorted(times)[len(times) // 2]
     return {"snapshots": 32, "total_GB": nbytes / 1e9, "seconds": dt, "GBps": nbytes / dt / 1e9, "reps": reps,
-            "seconds_each": times, "precision": prec, "all_ok": ok, "max_rel_err": rel}
+            "seconds_each": times, "precision": prec, "all_ok": ok, "max_rel_err": rel,
+            "paths": {("persistent" if k == 2 else "streaming" if k == 1 else "general"): v for k, v in paths.items()},
+            "tiles": {N: ctx.get_tile(N, prec) for N in (5, 7, 9)}}
 
 
-def run_serving(pool, prec, budget, n_req, rate_frac, tune_path=None):
-    """Config 5: Poisson arrivals, E lognormal (median 20k, sigma 1, clip
-    1k-500k), N uniform in {5,7,9}, continuous batching under an HBM budget."""
-    import numpy as np
+def run_hybrid(u, order, prec, steps, host_threads=12, codecs=(("bzip2", 9, False), ("zlib", 6, True))):
+    """The paper's hybrid approach: the lossy step on the GPU, each blob then
+    coded losslessly on separate host threads while the GPU goes on.  Per
+    codec: ms per GPU compression alone and with the lossless stage running
+    beside it (the difference is the stall the hybrid stage adds to the GPU),
+    the host time per blob, and the compression ratio of the whole chain."""
     import torch
 
     from paper_2407_20731_amd import isr
 
-    rng = np.random.default_rng(5)
+    out = {"host_threads": host_threads, "steps": steps, "codecs": []}
+    with isr.Context(device=0, host_threads=host_threads) as ctx:
+        for _ in range(2):
+            ctx.compress(u, order, TOL, prec).free()
+        # one untimed round of packing: the packer's pinned staging buffers
+        # (reused from then on) are allocated outside the timed region
+        warm = [ctx.compress(u, order, TOL, prec) for _ in range(steps)]
+        for j in [ctx.pack_submit(b, "zlib", 1) for b in warm]:
+            ctx.pack_poll(j, wait_ms=-1)
+        for b in warm:
+            b.free()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.compress(u, order, TOL, prec).free()
+        alone = (time.perf_counter() - t0) / steps * 1e3
+        out["gpu_ms_alone"] = alone
+        for codec, level, shuffle in codecs:
+            pend = []
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                b = ctx.compress(u, order, TOL, prec)
+                pend.append((b, ctx.pack_submit(b, codec, level, shuffle)))
+            gpu = (time.perf_counter() - t0) / steps * 1e3
+            t_sub = time.perf_counter()
+            secs, sizes, blob_bytes, in_bytes = [], [], 0, 0
+            for b, j in pend:
+                packed, s_ = ctx.pack_poll(j, wait_ms=-1)
+                secs.append(s_)
+                sizes.append(len(packed))
+                blob_bytes, in_bytes = b.stats["blob_bytes"], b.stats["in_bytes"]
+                b.free()
+            drain = time.perf_counter() - t_sub
+            host_per_blob = (drain + gpu * steps / 1e3) / steps
+            out["codecs"].append({"codec": f"{codec}-{level}" + ("+shuffle" if shuffle else ""),
+                                  "gpu_ms_with_lossless": gpu, "gpu_stall_ms": gpu - alone,
+                                  "host_s_per_blob": host_per_blob, "host_GBps_field": in_bytes / host_per_blob / 1e9,
+                                  "cr_lossy": (in_bytes - blob_bytes) / in_bytes,
+                                  "cr_lossy_lossless": (in_bytes - sizes[-1]) / in_bytes,
+                                  "packed_bytes": sizes[-1], "blob_bytes": blob_bytes})
+    return out
+
+
+def serving_requests(pool, n_req, seed=5):
+    """E lognormal (median 20k, sigma 1, clipped 1k-500k), N uniform in {5,7,9}."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
     reqs = []
     for _ in range(n_req):
         N = int(rng.choice([5, 7, 9]))
         E = int(np.clip(round(math.exp(rng.normal(math.log(20000), 1.0))), 1000, 500000))
         off = int(rng.integers(0, pool[N].shape[1] - E + 1))
         reqs.append((N, off, E))
-    with isr.Context(device=0, budget_bytes=budget, max_inflight=8, autotune_path=tune_path) as ctx:
+    return reqs
+
+
+def run_serving(pool, prec, budget, n_req, rate_fracs, slots, warm=50, tune_path=None):
+    """Config 5: open-loop Poisson arrivals of compression requests (sizes as
+    serving_requests), continuous batching under an HBM budget with `slots`
+    requests resident at most.  First the saturated (closed-loop) rate on the
+    same size mix; then, for each fraction of it, `warm` untimed requests and
+    `n_req` timed ones arriving at exponential gaps.  Latency = completion
+    time minus the scheduled arrival time (so submit and poll overheads and
+    queueing count)."""
+    import numpy as np
+    import torch
+
+    from paper_2407_20731_amd import isr
+
+    reqs = serving_requests(pool, warm + n_req)
+    out = {"slots": slots, "budget_GB": budget / 2 ** 30, "precision": prec, "requests": n_req, "warmup": warm,
+           "loads": []}
+    with isr.Context(device=0, budget_bytes=budget, max_inflight=slots, autotune_path=tune_path) as ctx:
         def submit(r):
             N, off, E = r
             return ctx.submit(pool[N][:, off:off + E], N, TOL, prec)
-        # saturated (closed-loop) rate on the first 48 requests
+
+        # the arena grows to the mix's working set outside the timed runs:
+        # the largest requests once, eight at a time
+        big = sorted(reqs, key=lambda r: -r[2] * (r[0] + 1) ** 3)[:2 * slots]
+        for i in [submit(r) for r in big]:
+            ctx.poll(i, wait_ms=-1).free()
+        # saturated rate: everything submitted at once, polled to the end
         torch.cuda.synchronize()
+        sat_reqs = reqs[:200]
         t0 = time.perf_counter()
-        ids = [submit(r) for r in reqs[:48]]
+        ids = [submit(r) for r in sat_reqs]
         for i in ids:
             ctx.poll(i, wait_ms=-1).free()
-        sat = 48 / (time.perf_counter() - t0)
-        rate = rate_frac * sat
-        # open loop: arrivals at exponential gaps, polled as they finish
-        gaps = rng.exponential(1.0 / rate, size=n_req)
-        arrive = np.cumsum(gaps)
-        pending, lat, nbytes = {}, [], 0
-        t0 = time.perf_counter()
-        k = 0
-        while k < n_req or pending:
-            now = time.perf_counter() - t0
-            while k < n_req and arrive[k] <= now:
-                pending[submit(reqs[k])] = reqs[k]
-                k += 1
-            for rid in list(pending):
-                b = ctx.poll(rid, wait_ms=0)
-                if b is not None:
-                    N, off, E = pending.pop(rid)
-                    lat.append((b.stats["t_done"] - b.stats["t_submit"]) * 1e3)
-                    nbytes += NCOMP * E * (N + 1) ** 3 * 8
-                    b.free()
-            time.sleep(0.0002)
-        wall = time.perf_counter() - t0
-    lat = np.array(lat)
-    return {"requests": n_req, "rate_per_s": rate, "saturated_rate_per_s": sat, "p50_ms": float(np.percentile(lat, 50)),
-            "p99_ms": float(np.percentile(lat, 99)), "GBps": nbytes / wall / 1e9, "precision": prec,
-            "budget_GB": budget / 2 ** 30}
+        sat = len(sat_reqs) / (time.perf_counter() - t0)
+        out["saturated_rate_per_s"] = sat
+        rng = np.random.default_rng(55)
+        for frac in rate_fracs:
+            rate = frac * sat
+            arrive = np.cumsum(rng.exponential(1.0 / rate, size=len(reqs)))
+            pending, lat, nbytes, done_t = {}, [], 0, []
+            t0 = time.perf_counter()
+            k = 0
+            while k < len(reqs) or pending:
+                now = time.perf_counter() - t0
+                while k < len(reqs) and arrive[k] <= now:
+                    pending[submit(reqs[k])] = k
+                    k += 1
+                for rid in list(pending):
+                    b = ctx.poll(rid, wait_ms=0)
+                    if b is not None:
+                        kk = pending.pop(rid)
+                        if kk >= warm:
+                            N, off, E = reqs[kk]
+                            lat.append((b.stats["t_done"] - (t0 + arrive[kk])) * 1e3)
+                            nbytes += NCOMP * E * (N + 1) ** 3 * 8
+                            done_t.append(b.stats["t_done"])
+                        b.free()
+                if k < len(reqs):
+                    time.sleep(max(0.0, min(0.0002, arrive[k] - (time.perf_counter() - t0))))
+            # throughput over the timed requests' span (first arrival to last completion)
+            span = max(done_t) - (t0 + arrive[warm])
+            lat = np.array(lat)
+            out["loads"].append({"load": frac, "rate_per_s": rate, "p50_ms": float(np.percentile(lat, 50)),
+                                 "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+                                 "GBps": nbytes / span / 1e9, "seconds": span})
+    return out
 
 
 def main() -> int:
@@ -364,7 +455,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--no-hybrid", action="store_true", help="skip the hybrid lossless stage section")
+    ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--order", type=int, default=ORDER, help="order N of the single-snapshot section")
     ap.add_argument("--elements", type=int, default=E_BENCH, help="elements of the single-snapshot section")
     ap.add_argument("--tile", type=int, default=None,
@@ -490,6 +582,20 @@ def main() -> int:
     }
     if "fp64" in results and head != "fp64":
         out["speedup_vs_fp64"] = results["fp64"]["ms"] / r["ms"]
+    if (E, N) == (E_BENCH, ORDER) and args.precision == "auto":
+        # the same snapshot on the FP64 path at tol 1e-5, and the 512-element
+        # snapshot (8^3 elements of the [0, 2pi)^3 box, seed 1) per call
+        r5 = time_single(ctx_run, u, "fp64", max(2, args.steps // 3), 1, stream, N, tol=1e-5)
+        out["fp64_tol_1e-5"] = {"GBps": (nvals * 8) / (r5["ms"] / 1e3) / 1e9, "ms": r5["ms"],
+                                "max_rel_err": r5["max_rel"], "kept_fraction": r5["kept"] / nvals,
+                                "status": r5["status"]}
+        u512 = torch.from_numpy(synth.field(512, 7, ncomp=NCOMP, seed=1)).cuda()
+        out["config1_latency_ms"] = {p: time_single(ctx_run, u512, p, 20, 3, stream, 7)["ms"] for p in precs}
+        del u512
+        log(f"fp64 tol 1e-5: {out['fp64_tol_1e-5']}; 512 elements: {out['config1_latency_ms']}")
+    if not args.no_hybrid and head != "fp64":
+        out["hybrid_lossless"] = run_hybrid(u, N, head, 5)
+        log(f"hybrid lossless: {out['hybrid_lossless']}")
     gpu_res = {}
     if not args.no_cpu and (E, N) == (CPU_SAMPLE_ELEMS, ORDER):
         # one more (untimed) result per precision, kept on the host for the
@@ -518,14 +624,20 @@ def main() -> int:
                 out["batch"] = run_batch(bctx, pool, head)
                 log(f"batch: {out['batch']}")
             if head != "fp64":
-                # the same batch as one streaming pipeline per snapshot on the scheduler's streams
+                # the same batch as one persistent launch of the streaming path
                 with isr.Context(device=0, budget_bytes=128 << 30, autotune_path=tune_path,
-                                 flags=isr.FLAG_BATCH_STREAMS) as pctx:
-                    out["batch_streams"] = run_batch(pctx, pool, head)
-                    log(f"batch, per-snapshot pipelines on streams: {out['batch_streams']}")
+                                 flags=isr.FLAG_BATCH_PERSISTENT) as pctx:
+                    out["batch_persistent"] = run_batch(pctx, pool, head)
+                    log(f"batch, one persistent launch: {out['batch_persistent']}")
         if not args.no_serving:
-            out["serving"] = run_serving(pool, "fp32", 64 << 30, args.serving_requests, 0.7, tune_path)
-            log(f"serving: {out['serving']}")
+            runs = {}
+            for slots in (4, 8):
+                runs[slots] = run_serving(pool, "fp32", 64 << 30, args.serving_requests, (0.5, 0.7, 0.9), slots,
+                                          tune_path=tune_path)
+                log(f"serving, {slots} slots: {runs[slots]}")
+            best = max(runs, key=lambda k: runs[k]["saturated_rate_per_s"])
+            out["serving"] = runs[best]
+            out["serving_other_slots"] = runs[4 if best == 8 else 8]
         del pool
     if not args.no_cpu:
         log("timing the CPU oracle sample")

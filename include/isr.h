@@ -70,8 +70,9 @@ extern "C" {
 
 /* ---- context flags ---------------------------------------------------- */
 #define ISR_FLAG_TIMING 1u  /* record device time per phase into isr_stats */
-#define ISR_FLAG_BATCH_STREAMS 2u /* FP32/BF16 batches: one streaming pipeline per snapshot on the
-                                     scheduler's streams instead of one persistent launch */
+#define ISR_FLAG_BATCH_PERSISTENT 4u /* FP32/BF16 batches of 8 snapshots or more, orders 5/7/9: one
+                                        persistent launch of the streaming path instead of one
+                                        streaming pipeline per snapshot on the scheduler's streams */
 
 #define ISR_MAX_COMP 8
 #define ISR_MAX_ORDER 15
@@ -85,7 +86,8 @@ typedef struct {
   uint32_t flags;            /* ISR_FLAG_* */
   uint64_t hbm_budget_bytes; /* cap on device memory the library holds; 0 = 64 GiB */
   int32_t max_inflight;      /* isr_submit: requests resident at once; 0 = 8 */
-  int32_t reserved;
+  int32_t host_threads;      /* isr_pack_submit: host threads of the lossless
+                                stage; 0 = 12 (or the host's cores, if fewer) */
   const char *autotune_path; /* optional tile-shape table: read at create when
                                 present, written by isr_autotune; NULL = none */
 } isr_config;
@@ -213,11 +215,14 @@ int isr_compress_noalloc(isr_ctx *ctx, const isr_field *f, void *d_out, uint64_t
                          isr_stats *st);
 
 /* Compress several snapshots (orders may differ) in one batched launch
- * sequence: one persistent launch when every snapshot has order 5, 7 or 9
- * (FP32 / BF16: at least 8 snapshots, each with the tile shape the context
- * holds for its order and precision -- built-in or set by isr_autotune /
- * isr_set_tile; the kernel holds every candidate shape), else one pipeline
- * per snapshot on the scheduler's streams.  outs[i] / st[i] as in isr_compress; returns the first non-OK
+ * sequence.  FP64 snapshots of orders 5, 7 and 9: one persistent launch of
+ * the general passes.  FP32 / BF16: one streaming pipeline per snapshot on
+ * the scheduler's streams, largest first; with ISR_FLAG_BATCH_PERSISTENT and
+ * at least 8 snapshots of orders 5, 7 and 9, one persistent launch of the
+ * streaming path, each snapshot with the tile shape the context holds for
+ * its order and precision (built-in, or set by isr_autotune / isr_set_tile;
+ * the kernel holds every candidate shape).  Other batches: one pipeline per
+ * snapshot.  Results are the same in every form.  outs[i] / st[i] as in isr_compress; returns the first non-OK
  * status (each st[i].status holds its own).  Footprint of the whole batch must
  * fit the budget (ISR_ENOMEM otherwise). */
 int isr_compress_batch(isr_ctx *ctx, const isr_field *fs, int32_t count, isr_blob **outs,
@@ -273,6 +278,46 @@ int isr_blob_size(const isr_blob *b, uint64_t *bytes);
 int isr_blob_to_host(const isr_blob *b, void *buf, uint64_t cap);
 int isr_blob_from_host(isr_ctx *ctx, const void *buf, uint64_t n, isr_blob **out);
 void isr_blob_free(isr_blob *b);
+
+/* ---- hybrid lossless stage (host CPU cores) ------------------------------
+ * The paper's hybrid approach (arXiv 2407.20731, Sec. III-A, IV-B): the lossy
+ * step runs synchronously on the GPU, and its output is then coded
+ * losslessly on separate host cores, asynchronously, while the GPU goes on.
+ * Packed format (little endian): "ISRZ", u32 version = 1, u32 codec, u32
+ * flags, u64 raw bytes, u32 chunk count K, u32 raw bytes per chunk, K x u64
+ * coded chunk sizes, then the K independently coded chunks of the raw
+ * stream.  The raw stream is the serialized blob; with ISR_PACK_SHUFFLE its
+ * kept values are stored byte plane by byte plane.  Compression ratio of the
+ * whole chain: (input bytes - packed bytes) / input bytes (Sec. IV-C). */
+#define ISR_CODEC_ZLIB 1   /* deflate (zlib), levels 0-9 */
+#define ISR_CODEC_BZIP2 2  /* bzip2, block sizes 1-9 (x 100 kB) */
+#define ISR_PACK_SHUFFLE 1u
+
+/* Host-only: code a serialized blob (isr_blob_to_host bytes) with `threads`
+ * host threads (0 = 12 or the host's cores).  out == NULL: only *out_bytes
+ * (the packed size).  Errors: ISR_EINVAL (bad codec, level, flags or blob,
+ * short buffer). */
+int isr_pack_host(const void *blob, uint64_t n, int32_t codec, int32_t level, uint32_t flags, int32_t threads,
+                  void *out, uint64_t cap, uint64_t *out_bytes);
+
+/* Host-only: decode a packed blob back to the serialized blob (out == NULL:
+ * only its size in *out_bytes).  Errors: ISR_EINVAL (corrupt input, short
+ * buffer). */
+int isr_unpack_host(const void *packed, uint64_t n, void *out, uint64_t cap, uint64_t *out_bytes);
+
+/* Queue a device blob for lossless coding on the context's host threads:
+ * its bytes are copied to pinned host memory on the packer's own stream
+ * (asynchronous to the caller's and the compression streams) and coded in
+ * submission order.  The blob must stay unfreed until the job completes.
+ * Errors: ISR_EINVAL, ISR_ENOMEM (pinned staging), ISR_EDEVICE. */
+int isr_pack_submit(isr_ctx *ctx, const isr_blob *b, int32_t codec, int32_t level, uint32_t flags, uint64_t *job);
+
+/* Poll a packing job: ISR_PENDING while it runs (wait_ms as isr_poll); then
+ * *out_bytes = packed size and *seconds = submit-to-done time.  With out ==
+ * NULL the job stays (size query); with a buffer of cap >= the size the bytes
+ * are copied and the job is retired.  Errors: ISR_ENOTFOUND, ISR_EINVAL. */
+int isr_pack_poll(isr_ctx *ctx, uint64_t job, int32_t wait_ms, void *out, uint64_t cap, uint64_t *out_bytes,
+                  double *seconds);
 
 /* ---- tile shapes and the autotuner --------------------------------------
  * The FP32 / BF16 streaming passes come in several tile shapes per order.

@@ -180,6 +180,9 @@ int resident_fp32(int kind, int order);
 int resident_bf16(int kind, int order);
 // order-independent kernels (isr_select.hip)
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// copy of the per-component states into mapped pinned host memory (host_dst
+// from hipHostMalloc with hipHostMallocMapped), by a kernel
+hipError_t launch_state_out(const CompState* src, CompState* host_dst, int ncomp, hipStream_t s);
 hipError_t launch_select1(const Job& j, int sample, hipStream_t s);
 hipError_t launch_refine(const Job& j, int level, int grid_x, hipStream_t s);
 hipError_t launch_select(const Job& j, int level, hipStream_t s);

@@ -237,6 +237,7 @@ struct isr_ctx {
   DevTables tab[ISR_MAX_ORDER + 1];
   std::mutex mu;  // serialises device pipelines
   std::unique_ptr<isr::Scheduler> sched;
+  isr::Packer* packer = nullptr;  // hybrid lossless stage on host threads
   int max_inflight = 8;
   std::atomic<int> tile[ISR_MAX_ORDER + 1][3];  // tile shape per (order, precision); -1 = built-in
   std::string tune_path;           // tile table file (read at create, written by the autotuner)
@@ -634,7 +635,8 @@ static CompState* grab_host_state(isr_ctx* c) {
   std::lock_guard<std::mutex> g(c->host_mu);
   if (c->host_free.empty()) {
     CompState* p = nullptr;
-    if (hipHostMalloc((void**)&p, sizeof(CompState) * ISR_MAX_COMP, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&p, sizeof(CompState) * ISR_MAX_COMP, hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess) {
       (void)hipGetLastError();
       return nullptr;
     }
@@ -655,7 +657,7 @@ static void put_host_state(isr_ctx* c, CompState* p) {
 static int task_enqueue(Task* t) {
   int rc = enqueue_pipeline(t->c, t->j, t->z, t->s, t->timing ? t->ev : nullptr, t->fast);
   if (rc) return rc;
-  HIPCHK(hipMemcpyAsync(t->hs, t->j.st, sizeof(CompState) * t->f.ncomp, hipMemcpyDeviceToHost, t->s));
+  HIPCHK(launch_state_out(t->j.st, t->hs, t->f.ncomp, t->s));
   HIPCHK(hipEventRecord(t->done, t->s));
   return ISR_OK;
 }
@@ -991,7 +993,7 @@ static int run_batch_stream(isr_ctx* c, const isr_field* fs, int count, isr_blob
       break;
     }
     for (int i = 0; i < count; ++i)
-      (void)hipMemcpyAsync(sn[i].hs, sn[i].j.st, sizeof(CompState) * fs[i].ncomp, hipMemcpyDeviceToHost, s);
+      (void)launch_state_out(sn[i].j.st, sn[i].hs, fs[i].ncomp, s);
     (void)hipMemcpyAsync(&err_host, B.err, sizeof(int), hipMemcpyDeviceToHost, s);
     if (hipStreamSynchronize(s) != hipSuccess) {
       rc = fail(ISR_EDEVICE, "batch failed: %s", hipGetErrorString(hipGetLastError()));
@@ -1063,9 +1065,14 @@ int run_batch(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_s
     if (p != ISR_PREC_FP64) persistent = false;
     if (p == ISR_PREC_FP64 || !stream || !fbatch_shape(o, ctx_tile(c, o, p))) stream = false;
   }
-  // (a handful of snapshots keeps the phases of one snapshot apart in the
-  // queue and leaves most workgroups waiting: their own pipelines are faster)
-  if (stream && count >= FBATCH_MIN && !(c->flags & ISR_FLAG_BATCH_STREAMS))
+  // The persistent streaming launch is opt-in: every queue item publishes its
+  // results to later phases through device-scope release/acquire counters,
+  // and on gfx950 each such fence writes back and invalidates an XCD's L2;
+  // over tens of thousands of items that costs more than the per-snapshot
+  // launches it saves (measured: 32 snapshots, 26.8 GB, BF16: 61 ms in one
+  // persistent launch, 27 ms as stream pipelines).  A handful of snapshots
+  // also keeps the phases of one snapshot apart in the queue.
+  if (stream && count >= FBATCH_MIN && (c->flags & ISR_FLAG_BATCH_PERSISTENT))
     return run_batch_stream(c, fs, count, outs, st);
   if (!persistent) return run_batch_concurrent(c, fs, count, outs, st);
   const int prec = fs[0].precision;
@@ -1192,7 +1199,7 @@ int run_batch(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_s
       break;
     }
     for (int i = 0; i < count; ++i)
-      (void)hipMemcpyAsync(sn[i].hs, sn[i].j.st, sizeof(CompState) * fs[i].ncomp, hipMemcpyDeviceToHost, s);
+      (void)launch_state_out(sn[i].j.st, sn[i].hs, fs[i].ncomp, s);
     (void)hipMemcpyAsync(&err_host, B.err, sizeof(int), hipMemcpyDeviceToHost, s);
     if (hipStreamSynchronize(s) != hipSuccess) {
       rc = fail(ISR_EDEVICE, "batch failed: %s", hipGetErrorString(hipGetLastError()));
@@ -1327,10 +1334,12 @@ int isr_create(const isr_config* cfg, isr_ctx** out) {
   }
   int rc = upload_tables(c.get());
   if (rc) return rc;
-  HIPCHK(hipHostMalloc((void**)&c->st_host, sizeof(CompState) * ISR_MAX_COMP, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&c->st_host, sizeof(CompState) * ISR_MAX_COMP, hipHostMallocMapped | hipHostMallocCoherent));
   rc = isr::noalloc_init(c->device);  // address of the allocation-free entry point's scratch on this GPU
   if (rc) return rc;
   c->sched.reset(new isr::Scheduler(c.get()));
+  c->packer = isr::packer_create(c->device, d.host_threads);
+  if (!c->packer) return fail(ISR_EDEVICE, "could not create the lossless packer");
   *out = c.release();
   return ISR_OK;
 }
@@ -1339,6 +1348,8 @@ int isr_destroy(isr_ctx* c) {
   if (!c) return fail(ISR_EINVAL, "ctx is NULL");
   (void)hipSetDevice(c->device);
   c->sched.reset();
+  isr::packer_destroy(c->packer);
+  c->packer = nullptr;
   (void)hipDeviceSynchronize();
   c->arena.reset();
   if (c->tables_dev) (void)hipFree(c->tables_dev);
@@ -1662,6 +1673,27 @@ int isr_blob_from_host(isr_ctx* c, const void* buf, uint64_t nbytes, isr_blob** 
   return ISR_OK;
 }
 
+int isr_pack_submit(isr_ctx* c, const isr_blob* b, int32_t codec, int32_t level, uint32_t flags, uint64_t* job) {
+  if (!c || !b || !job) return fail(ISR_EINVAL, "ctx, blob or job is NULL");
+  if (b->ctx != c) return fail(ISR_EINVAL, "the blob belongs to another context");
+  if ((codec != ISR_CODEC_ZLIB || level < 0 || level > 9) && (codec != ISR_CODEC_BZIP2 || level < 1 || level > 9))
+    return fail(ISR_EINVAL, "codec %d with level %d is not supported (zlib 0-9, bzip2 1-9)", codec, level);
+  if (flags & ~(uint32_t)ISR_PACK_SHUFFLE) return fail(ISR_EINVAL, "unknown packing flags 0x%x", flags);
+  int rc = set_device(c);
+  if (rc) return rc;
+  char hdr[isr_blob::HDR + isr_blob::CHDR * ISR_MAX_COMP];
+  put_hdr(b, hdr);
+  const size_t hb = isr_blob::HDR + isr_blob::CHDR * b->ncomp;
+  const size_t body = b->bitmap_bytes() + b->ptr_bytes() + b->values_bytes();
+  return isr::packer_submit(c->packer, (const unsigned char*)hdr, hb, b->bitmap(), body, codec, level, flags, job);
+}
+
+int isr_pack_poll(isr_ctx* c, uint64_t job, int32_t wait_ms, void* out, uint64_t cap, uint64_t* out_bytes,
+                  double* seconds) {
+  if (!c) return fail(ISR_EINVAL, "ctx is NULL");
+  return isr::packer_poll(c->packer, job, wait_ms, out, cap, out_bytes, seconds);
+}
+
 void isr_blob_free(isr_blob* b) {
   if (!b) return;
   if (b->ctx && b->dev) {
@@ -1725,7 +1757,7 @@ int run_compress_noalloc(isr_ctx* c, const isr_field* f, char* scratch, size_t s
   for (;;) {
     rc = enqueue_pipeline(c, j, z, s, nullptr, fast);
     if (rc) return rc;
-    HIPCHK(hipMemcpyAsync(hs, j.st, sizeof(CompState) * nc, hipMemcpyDeviceToHost, s));
+    HIPCHK(launch_state_out(j.st, hs, nc, s));
     HIPCHK(hipStreamSynchronize(s));
     int flags = 0;
     for (int k = 0; k < nc; ++k) flags |= hs[k].flags;

@@ -81,6 +81,14 @@ int run_compress_noalloc(isr_ctx* c, const isr_field* f, char* scratch, size_t s
                          uint64_t out_cap, uint64_t* out_bytes, isr_stats* st);
 // set the calling thread's isr_last_error() text and return code
 int set_error(int code, const char* fmt, ...);
+// Hybrid lossless stage (isr_lossless.cpp): a context's packer codes blobs on
+// host threads, after copying each to pinned memory on the packer's stream.
+struct Packer;
+Packer* packer_create(int device, int threads);
+void packer_destroy(Packer* p);
+int packer_submit(Packer* p, const unsigned char* hdr, size_t hb, const void* dev_body, size_t body, int codec,
+                  int level, uint32_t flags, uint64_t* job);
+int packer_poll(Packer* p, uint64_t job, int wait_ms, void* out, uint64_t cap, uint64_t* out_bytes, double* secs);
 int ctx_device(const isr_ctx* c);
 Arena* ctx_arena(isr_ctx* c);
 int ctx_max_inflight(const isr_ctx* c);

@@ -14,6 +14,22 @@ __global__ void k_zero(u64* p, size_t nwords) {
   for (; i < nwords; i += stride) p[i] = 0ull;
 }
 
+// Per-component state to mapped pinned host memory, written by the GPU (no
+// DMA copy: a small copy would queue behind bulk transfers on the copy
+// engines, e.g. a blob going to the lossless stage).
+__global__ __launch_bounds__(64) void k_state_out(const u64* src, u64* dst, int nwords) {
+  for (int i = threadIdx.x; i < nwords; i += 64) dst[i] = src[i];
+}
+
+hipError_t launch_state_out(const CompState* src, CompState* host_dst, int ncomp, hipStream_t s) {
+  void* d = nullptr;
+  hipError_t e = hipHostGetDevicePointer(&d, host_dst, 0);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_state_out, dim3(1), dim3(64), 0, s, (const u64*)src, (u64*)d,
+                     (int)(sizeof(CompState) * ncomp / 8));
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   size_t nw = bytes / 8;
   if (nw == 0) return hipSuccess;

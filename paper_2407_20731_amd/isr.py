@@ -29,7 +29,7 @@ LIB_PATH = os.path.join(_HERE, "libisr.so")
 OK, PENDING, EINVAL, ENOMEM, EDEVICE, ETOL, ECANCELED, ENOTFOUND = 0, 1, -1, -2, -3, -4, -5, -6
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 FLAG_TIMING = 1
-FLAG_BATCH_STREAMS = 2  # FP32/BF16 batches on the scheduler's streams instead of one persistent launch
+FLAG_BATCH_PERSISTENT = 4  # FP32/BF16 batches (>= 8, orders 5/7/9) as one persistent launch
 FIELD_COPY = 1  # isr_field.flags: copy-on-submit
 MAX_COMP = 8
 NPHASE = 9
@@ -47,7 +47,7 @@ class IsrError(RuntimeError):
 
 class isr_config(C.Structure):
     _fields_ = [("device", C.c_int32), ("flags", C.c_uint32), ("hbm_budget_bytes", C.c_uint64),
-                ("max_inflight", C.c_int32), ("reserved", C.c_int32), ("autotune_path", C.c_char_p)]
+                ("max_inflight", C.c_int32), ("host_threads", C.c_int32), ("autotune_path", C.c_char_p)]
 
 
 class isr_field(C.Structure):
@@ -101,6 +101,10 @@ def load_library(path: str = LIB_PATH):
         "isr_blob_free": (None, [P]),
         "isr_gll_tables": (I32, [I32] + [P] * 7),
         "isr_get_tile": (I32, [P, I32, I32, C.POINTER(I32)]),
+        "isr_pack_host": (I32, [P, U64, I32, I32, C.c_uint32, I32, P, U64, C.POINTER(U64)]),
+        "isr_unpack_host": (I32, [P, U64, P, U64, C.POINTER(U64)]),
+        "isr_pack_submit": (I32, [P, P, I32, I32, C.c_uint32, C.POINTER(U64)]),
+        "isr_pack_poll": (I32, [P, U64, I32, P, U64, C.POINTER(U64), C.POINTER(C.c_double)]),
         "isr_set_tile": (I32, [P, I32, I32, I32]),
         "isr_autotune": (I32, [P, C.POINTER(isr_field), I32, C.POINTER(isr_tune_report)]),
     }
@@ -139,6 +143,31 @@ def gll_tables(order: int) -> Dict[str, np.ndarray]:
     out["w3"] = out["w3"].reshape(n, n, n)
     out["g3"] = out["g3"].reshape(n, n, n)
     return out
+
+
+CODECS = {"zlib": 1, "bzip2": 2}
+PACK_SHUFFLE = 1
+
+
+def pack_host(blob_bytes: bytes, codec="zlib", level: int = 6, shuffle: bool = False, threads: int = 0) -> bytes:
+    """Lossless coding of a serialized blob on host threads (no GPU)."""
+    lib = load_library()
+    n = C.c_uint64()
+    args = (blob_bytes, len(blob_bytes), CODECS[codec], level, PACK_SHUFFLE if shuffle else 0, threads)
+    _check(lib.isr_pack_host(*args, None, 0, C.byref(n)), "isr_pack_host")
+    buf = C.create_string_buffer(n.value)
+    _check(lib.isr_pack_host(*args, buf, n.value, C.byref(n)), "isr_pack_host")
+    return buf.raw[:n.value]
+
+
+def unpack_host(packed: bytes) -> bytes:
+    """Inverse of pack_host."""
+    lib = load_library()
+    n = C.c_uint64()
+    _check(lib.isr_unpack_host(packed, len(packed), None, 0, C.byref(n)), "isr_unpack_host")
+    buf = C.create_string_buffer(n.value)
+    _check(lib.isr_unpack_host(packed, len(packed), buf, n.value, C.byref(n)), "isr_unpack_host")
+    return buf.raw[:n.value]
 
 
 def _stats_dict(st: isr_stats, ncomp: int) -> dict:
@@ -254,10 +283,10 @@ def _stream_ptr(stream) -> int:
 
 class Context:
     def __init__(self, device: int = 0, budget_bytes: int = 0, flags: int = 0, max_inflight: int = 0,
-                 autotune_path: Optional[str] = None):
+                 autotune_path: Optional[str] = None, host_threads: int = 0):
         lib = load_library()
         cfg = isr_config(device=device, flags=flags, hbm_budget_bytes=budget_bytes, max_inflight=max_inflight,
-                         autotune_path=autotune_path.encode() if autotune_path else None)
+                         host_threads=host_threads, autotune_path=autotune_path.encode() if autotune_path else None)
         h = C.c_void_p()
         self._blobs = weakref.WeakSet()
         self._h = C.c_void_p(0)
@@ -400,6 +429,26 @@ class Context:
         out = torch.empty((f.ncomp, f.n_elem, n, n, n), dtype=dt, device=u.device)
         _check(load_library().isr_forward(self._h, C.byref(f), C.c_void_p(out.data_ptr())), "isr_forward")
         return out
+
+    def pack_submit(self, blob: Blob, codec="zlib", level: int = 6, shuffle: bool = False) -> int:
+        """Queue the blob for lossless coding on the context's host threads."""
+        job = C.c_uint64()
+        _check(load_library().isr_pack_submit(self._h, blob.handle, CODECS[codec], level,
+                                              PACK_SHUFFLE if shuffle else 0, C.byref(job)), "isr_pack_submit")
+        return job.value
+
+    def pack_poll(self, job: int, wait_ms: int = 0):
+        """None while pending, else (packed bytes, seconds from submit to done)."""
+        lib = load_library()
+        n = C.c_uint64()
+        secs = C.c_double()
+        rc = lib.isr_pack_poll(self._h, job, wait_ms, None, 0, C.byref(n), C.byref(secs))
+        if rc == PENDING:
+            return None
+        _check(rc, "isr_pack_poll")
+        buf = C.create_string_buffer(n.value)
+        _check(lib.isr_pack_poll(self._h, job, 0, buf, n.value, C.byref(n), C.byref(secs)), "isr_pack_poll")
+        return buf.raw[:n.value], secs.value
 
     def blob_from_bytes(self, buf: bytes) -> Blob:
         h = C.c_void_p()

@@ -3,9 +3,9 @@ sizes): every result must equal the same snapshot compressed alone, bit for
 bit (the global sums are exact, or fixed-order per lane with the same grids,
 so the queue order cannot change them); the FP64 members must equal the
 oracle, and the FP32 / BF16 members pass the oracle checks of
-tests/mixed_checks.py.  FP32 / BF16 batches run as one persistent launch of the streaming
-path; with FLAG_BATCH_STREAMS as one streaming pipeline per snapshot on the
-scheduler's streams, with the same results."""
+tests/mixed_checks.py.  FP32 / BF16 batches run as one streaming pipeline per
+snapshot on the scheduler's streams, or with FLAG_BATCH_PERSISTENT as one
+persistent launch of the streaming path, with the same results."""
 
 import numpy as np
 import pytest
@@ -35,24 +35,26 @@ def test_batch_equals_alone(isr_ctx, prec):
     snaps.append((5, 6000, torch.from_numpy(np.repeat(synth.field(1, 5, seed=5), 6000, axis=1)).cuda()))
     torch.cuda.synchronize()
     print(f"[case] batch prec={prec} sizes={[(N, E) for N, E, _ in snaps]}", flush=True)
-    blobs = isr_ctx.compress_batch([(u, N, 1e-3) for N, E, u in snaps], prec)
-    paths = [b.stats["path"] for b in blobs]
-    print(f"[batch] {prec} paths {paths}", flush=True)
-    if prec != "fp64":
-        assert paths.count(2) >= len(blobs) // 2  # the persistent launch (reruns alone aside)
-    for (N, E, u), b in zip(snaps, blobs):
-        assert b.status == 0
+    from paper_2407_20731_amd import isr
+    with isr.Context(flags=isr.FLAG_BATCH_PERSISTENT) as pctx:
+        blobs = pctx.compress_batch([(u, N, 1e-3) for N, E, u in snaps], prec)
+        paths = [b.stats["path"] for b in blobs]
+        print(f"[batch] {prec} paths {paths}", flush=True)
+        if prec != "fp64":
+            assert paths.count(2) >= len(blobs) // 2  # the persistent launch (reruns alone aside)
+        got = [b.to_bytes() for b in blobs]
+    for (N, E, u), g in zip(snaps, got):
         alone = isr_ctx.compress(u, N, 1e-3, prec)
-        same = b.to_bytes() == alone.to_bytes()  # (no assertion diff of MB-sized strings)
+        assert alone.status == 0
+        same = g == alone.to_bytes()  # (no assertion diff of MB-sized strings)
         assert same, (N, E)
     if prec != "fp64":
-        from paper_2407_20731_amd import isr
-        with isr.Context(flags=isr.FLAG_BATCH_STREAMS) as ctx2:
-            blobs2 = ctx2.compress_batch([(u, N, 1e-3) for N, E, u in snaps], prec)
-            assert all(b.stats["path"] != 2 for b in blobs2)
-            for (N, E, u), b, b2 in zip(snaps, blobs, blobs2):
-                same = b.to_bytes() == b2.to_bytes()
-                assert same, (N, E)
+        # the default form: one streaming pipeline per snapshot
+        blobs2 = isr_ctx.compress_batch([(u, N, 1e-3) for N, E, u in snaps], prec)
+        assert all(b.stats["path"] != 2 for b in blobs2)
+        for (N, E, u), g, b2 in zip(snaps, got, blobs2):
+            same = g == b2.to_bytes()
+            assert same, (N, E)
 
 
 @pytest.mark.parametrize("shapes", [{5: 2, 7: 1, 9: 0}, {5: 8, 7: 2, 9: 2}, {5: 0, 7: 0, 9: 1}])
@@ -64,7 +66,7 @@ def test_batch_persistent_takes_every_shape(shapes):
     rng = np.random.default_rng(15)
     snaps = _batch(rng, 9, 30, 2000, 1100)
     torch.cuda.synchronize()
-    with isr.Context() as ctx:
+    with isr.Context(flags=isr.FLAG_BATCH_PERSISTENT) as ctx:
         for N, t in shapes.items():
             ctx.set_tile(N, "bf16", t)
         print(f"[case] batch shapes {shapes} sizes={[(N, E) for N, E, _ in snaps]}", flush=True)
@@ -93,24 +95,29 @@ def test_batch_fp64_matches_oracle(isr_ctx):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_batch_mixed_matches_oracle(isr_ctx, prec):
-    """Every member of an FP32 / BF16 batch (ten snapshots: the persistent
-    launch) against the oracle with the checks of tests/mixed_checks.py,
-    its decompressed output included."""
+    """Every member of an FP32 / BF16 batch against the oracle with the checks
+    of tests/mixed_checks.py, its decompressed output included: ten snapshots
+    in one persistent launch, and the same batch as stream pipelines."""
     from mixed_checks import verify_mixed
+    from paper_2407_20731_amd import isr
     rng = np.random.default_rng(14)
     snaps = _batch(rng, 10, 20, 600, 1000)
     torch.cuda.synchronize()
     print(f"[case] batch oracle prec={prec} sizes={[(N, E) for N, E, _ in snaps]}", flush=True)
-    blobs = isr_ctx.compress_batch([(u, N, 1e-3) for N, E, u in snaps], prec)
-    assert [b.stats["path"] for b in blobs].count(2) >= len(blobs) // 2
-    for (N, E, u), b in zip(snaps, blobs):
-        assert b.status == 0
-        u_np = u.cpu().numpy()
-        coef = isr_ctx.forward(u, N, prec).cpu().numpy().astype(np.float64)
-        out = isr_ctx.decompress(b).cpu().numpy()
-        ref = oracle.compress(u_np, N, 1e-3, keep_arrays=True)
-        rep = verify_mixed(b.arrays(), b.status, b.stats["repair_iters"], u_np, N, 1e-3, prec, coef, ref.comps, out=out)
-        print(f"[batch-oracle] {prec} N={N} E={E} path={b.stats['path']}: {rep}", flush=True)
+    refs = [oracle.compress(u.cpu().numpy(), N, 1e-3, keep_arrays=True) for N, E, u in snaps]
+    for flags in (isr.FLAG_BATCH_PERSISTENT, 0):
+        with isr.Context(flags=flags) as ctx:
+            blobs = ctx.compress_batch([(u, N, 1e-3) for N, E, u in snaps], prec)
+            paths = [b.stats["path"] for b in blobs]
+            if flags:
+                assert paths.count(2) >= len(blobs) // 2
+            for (N, E, u), b, ref in zip(snaps, blobs, refs):
+                assert b.status == 0
+                coef = ctx.forward(u, N, prec).cpu().numpy().astype(np.float64)
+                out = ctx.decompress(b).cpu().numpy()
+                rep = verify_mixed(b.arrays(), b.status, b.stats["repair_iters"], u.cpu().numpy(), N, 1e-3, prec, coef,
+                                   ref.comps, out=out)
+                print(f"[batch-oracle] {prec} N={N} E={E} path={b.stats['path']}: {rep}", flush=True)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
