@@ -23,6 +23,9 @@ relative L2 error bound -- as one data-parallel pass over the elements:
                   value threshold that enforces the bound, kept sets, the
                   compacted blob arrays, reconstruction, the error check and
                   the rounding repair.
+  * ``quantize``  a variant of the lossy step: the cut at a share of the
+                  budget, then JPEG-like uniform quantisation of the kept
+                  coefficients in the energy norm with the rest of it.
 
 Pins (what each function is checked against, in ``tests/test_oracle_*.py``):
 closed-form GLL rules, scipy's Gauss-Jacobi roots, quadrature exactness,
@@ -30,8 +33,11 @@ numpy's Legendre evaluator, unit coefficients of pure Legendre fields, exact
 keep-all round trip, discrete Parseval (with and without per-element
 Jacobians), norms re-measured with independent weights and exact rationals,
 math.fsum / Fraction sums, brute force over all subsets on tiny inputs,
-hand-computed repair budgets and a repair run to its cap, and bitmap words
-written out by hand for known kept sets.  Every function has such a pin.
+hand-computed repair budgets and a repair run to its cap, bitmap words
+written out by hand for known kept sets, and for the quantised variant its
+step against hand values, the per-coefficient error bound on random data and
+Parseval with independently summed coefficient-space errors.  Every
+function has such a pin.
 """
 
 from .tables import gll_tables, Tables  # noqa: F401

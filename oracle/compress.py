@@ -182,7 +182,7 @@ def repair_loop(cut_and_check, B: float, tol: float):
     return payload, B, it, (OK if rel <= tol else ETOL)
 
 
-def _compress_component(uc, T, tol, jac, keep_arrays):
+def _compress_component(uc, T, tol, jac, keep_arrays, budget_scale=1.0):
     coef = forward(uc, T.A)
     e = energies(coef, T.g3, jac)
     U2 = exact_sum(norm_terms(uc, T.w3, jac))
@@ -205,7 +205,10 @@ def _compress_component(uc, T, tol, jac, keep_arrays):
         rel, payload = cut_and_check(0.0)
         B, it, status = 0.0, 0, OK
     else:
-        payload, B, it, status = repair_loop(cut_and_check, (tol * tol) * U2, tol)
+        B0 = (tol * tol) * U2
+        if budget_scale != 1.0:
+            B0 = B0 * budget_scale  # a share of the budget left to a later stage
+        payload, B, it, status = repair_loop(cut_and_check, B0, tol)
     tau, S, keep, recon, err2, rel = payload
     counts = keep.reshape(keep.shape[0], -1).sum(axis=1).astype(np.uint64)
     elem_ptr = np.zeros(keep.shape[0] + 1, dtype=np.uint64)
@@ -221,8 +224,10 @@ def _compress_component(uc, T, tol, jac, keep_arrays):
 
 
 def compress(u: np.ndarray, order: int, tol: float, jac: Optional[np.ndarray] = None,
-             keep_arrays: bool = False) -> OracleResult:
-    """Compress u[ncomp, E, n, n, n] (FP64, i fastest) at relative tolerance tol."""
+             keep_arrays: bool = False, budget_scale: float = 1.0) -> OracleResult:
+    """Compress u[ncomp, E, n, n, n] (FP64, i fastest) at relative tolerance tol.
+    budget_scale < 1 cuts at ((tol*tol)*U2)*budget_scale instead of the full
+    budget (the quantised variant leaves the rest to its quantisation)."""
     u = np.asarray(u, dtype=np.float64)
     n = order + 1
     if u.ndim != 5 or u.shape[2:] != (n, n, n):
@@ -232,7 +237,7 @@ def compress(u: np.ndarray, order: int, tol: float, jac: Optional[np.ndarray] = 
     if math.isnan(tol):
         raise ValueError("tol is NaN")
     T = gll_tables(order)
-    comps = [_compress_component(u[c], T, float(tol), jac, keep_arrays) for c in range(u.shape[0])]
+    comps = [_compress_component(u[c], T, float(tol), jac, keep_arrays, budget_scale) for c in range(u.shape[0])]
     return OracleResult(order=order, tol=float(tol), comps=comps)
 
 
