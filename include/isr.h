@@ -200,7 +200,7 @@ int isr_compress(isr_ctx *ctx, const isr_field *f, isr_blob **out, isr_stats *st
  *   d_out      DEVICE pointer, 256-byte aligned, out_cap bytes; receives the
  *              serialized blob (the bytes isr_blob_to_host would give, layout
  *              below).  out_cap must hold the worst case (every coefficient
- *              kept): 56 + 64 ncomp + 8 ncomp n_elem W + 8 ncomp (n_elem + 1)
+ *              kept): 64 + 72 ncomp + 8 ncomp n_elem W + 8 ncomp (n_elem + 1)
  *              + ncomp n_elem n^3 value_bytes; otherwise ISR_EINVAL.
  *   out_bytes  receives the blob's size (on ISR_EINVAL for a short buffer:
  *              the size required).  May be NULL.
@@ -213,6 +213,24 @@ int isr_compress(isr_ctx *ctx, const isr_field *f, isr_blob **out, isr_stats *st
 #define ISR_NOALLOC_SCRATCH_BYTES (128ull << 20)
 int isr_compress_noalloc(isr_ctx *ctx, const isr_field *f, void *d_out, uint64_t out_cap, uint64_t *out_bytes,
                          isr_stats *st);
+
+/* Quantised variant of the lossy step (the JPEG-like form: the kept
+ * coefficients are quantised, as JPEG quantises the coefficients it keeps).
+ * FP64 path, unit Jacobians (f->elem_jac NULL), f->tol >= 0, 0 <= share < 1.
+ * Per component: the plain method's global cut at the budget
+ * ((tol*tol)*U2)*(1 - share) (dropped energy S_c, K kept), then each kept
+ * coefficient c (flat index f) coded as q = rint((c sqrt(g3_f)) / step) with
+ * step = (2 sqrt((B - S_c) / K)) (1 - 2^-20), B = (tol*tol)*U2, so that every
+ * code's error energy is at most (step/2)^2 and the total stays below B; the
+ * exact error of the dequantised field (values (q step) / sqrt(g3_f), FP64
+ * fixed-order inverse, the one isr_decompress uses) is measured, and the step
+ * is shrunk by (tol/rel)(1 - 2^-20) while rounding leaves it above tol (at
+ * most 4 times; then ISR_ETOL).  The blob holds the codes as FP32 integers
+ * (value kind 1) and the step per component; isr_decompress dequantises.
+ * Errors: as isr_compress; ISR_EINVAL for another precision, Jacobians, a
+ * negative tol or share outside [0, 1); ISR_ETOL when a code would need more
+ * than 24 bits. */
+int isr_compress_quantized(isr_ctx *ctx, const isr_field *f, double share, isr_blob **out, isr_stats *st);
 
 /* Compress several snapshots (orders may differ) in one batched launch
  * sequence.  FP64 snapshots of orders 5, 7 and 9: one persistent launch of
@@ -263,12 +281,15 @@ int isr_decompress(isr_ctx *ctx, const isr_blob *b, void *d_out, int32_t out_pre
 int isr_forward(isr_ctx *ctx, const isr_field *f, void *d_coef);
 
 /* Blob queries and (de)serialisation.  Serialized layout (little endian):
- *   "ISR1", u32 version=2, i32 order, i32 ncomp, i64 n_elem, i32 value_bytes
+ *   "ISR1", u32 version=3, i32 order, i32 ncomp, i64 n_elem, i32 value_bytes
  *   (8 or 4), i32 words_per_elem W = ceil(n^3/64), f64 tol, i32 precision,
  *   i32 status, i32 engine (FP32 / BF16: 0 general passes, 1 wave-tile or
  *   large-order engine, 2 dense-tile engine; 0 for FP64), i32 tile (the
- *   dense tile, else 0); then per component: f64 U2, B, tau, dropped, err2, rel_err,
- *   u64 kept, u64 values_offset; then all bitmaps [ncomp][n_elem][W] u64 (bit
+ *   dense tile, else 0), i32 value kind (0 coefficient values, 1
+ *   quantisation codes: integers held exactly by FP32, isr_compress_quantized),
+ *   i32 0; then per component: f64 U2, B, tau, dropped, err2, rel_err,
+ *   u64 kept, u64 values_offset, f64 quantisation step (0 unless value kind
+ *   1); then all bitmaps [ncomp][n_elem][W] u64 (bit
  *   f = p + n q + n^2 r of element e set iff kept), all offset tables
  *   [ncomp][n_elem + 1] u64 (per component, starting at 0), all kept values
  *   (component after component, element then f ascending). */

@@ -38,7 +38,7 @@ DEV void select_sample_body(const Job& j, int comp) {
     if (lane == 0) st->win_lo = st->win_hi = 0;
     return;
   }
-  const double B = (tol * tol) * st->samp_u2;
+  const double B = ((tol * tol) * st->samp_u2) * j.cut_scale;
   double cs = 0.0;
   u64 cc = 0;
   for (int k = 0; k < 32; ++k) {

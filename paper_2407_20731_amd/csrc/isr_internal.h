@@ -100,6 +100,7 @@ struct Job {
   int precision;
   int vbytes;          // 8 (FP64 values) or 4
   double tol;
+  double cut_scale;    // the cut's budget is ((tol*tol)*U2)*cut_scale (1: the whole budget)
   double Bov[8];       // per-component budget override (repair); < 0 = none
   DevTables tab;
   // scratch
@@ -131,6 +132,10 @@ struct Job {
   u64* elem_ptr;       // [ncomp][n_elem + 1]
   void* values;        // kept values, component after component
   u64* voff;           // [ncomp] offset of each component's first value
+  // quantised variant: per-component step of the codes (device), and the
+  // codes written by the quantisation pass (FP32 integers, values' layout)
+  const double* qstep;
+  float* qvals;
 };
 
 // Persistent batch launch (isr_batch.cuh): phases of the shared work queue.
@@ -164,7 +169,7 @@ int batch_resident_fp32(size_t lds);
 int batch_resident_bf16(size_t lds);
 
 // Streaming passes (isr_passes.cuh), one instantiation file per precision.
-enum PassKind { K_PASS1 = 0, K_PASS2 = 1, K_PASS3 = 2, K_DECOMP = 3, K_FORWARD = 4 };
+enum PassKind { K_PASS1 = 0, K_PASS2 = 1, K_PASS3 = 2, K_DECOMP = 3, K_FORWARD = 4, K_QUANT = 5 };
 int tiles_per_comp(int order, long long n_elem);
 int words_per_elem(int order);
 // grid: x extent (pass1/pass2 also get y = ncomp); extra: output pointer of
@@ -183,6 +188,9 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // copy of the per-component states into mapped pinned host memory (host_dst
 // from hipHostMalloc with hipHostMallocMapped), by a kernel
 hipError_t launch_state_out(const CompState* src, CompState* host_dst, int ncomp, hipStream_t s);
+// correctly rounded exact totals of the error histograms j.histR, per
+// component, into err2_out[ncomp] (device)
+hipError_t launch_err_total(const Job& j, double* err2_out, hipStream_t s);
 hipError_t launch_select1(const Job& j, int sample, hipStream_t s);
 hipError_t launch_refine(const Job& j, int level, int grid_x, hipStream_t s);
 hipError_t launch_select(const Job& j, int level, hipStream_t s);
@@ -299,9 +307,9 @@ int fbatch_resident_fp32(size_t lds);
 int fbatch_resident_bf16(size_t lds);
 
 // Allocation-free entry point (isr_noalloc.hip): header bytes of a
-// serialized blob (56 + 64 per component) written by a kernel, and the
+// serialized blob (64 + 72 per component) written by a kernel, and the
 // per-device lookup of the fixed scratch array's address.
-constexpr int ISR_NOALLOC_HDR_MAX = 56 + 64 * 8;
+constexpr int ISR_NOALLOC_HDR_MAX = 64 + 72 * 8;
 hipError_t launch_put_bytes(const void* src, int n, void* dst, hipStream_t s);
 int noalloc_init(int device);
 

@@ -59,7 +59,7 @@ struct BlobLayout {
 // full check happens when the blob is uploaded).
 BlobLayout blob_layout(const unsigned char* p, size_t n) {
   BlobLayout L;
-  if (n < 56 || std::memcmp(p, "ISR1", 4) != 0) return L;
+  if (n < 64 || std::memcmp(p, "ISR1", 4) != 0) return L;
   int32_t order, ncomp, vb, W;
   int64_t ne;
   std::memcpy(&order, p + 8, 4);
@@ -68,7 +68,7 @@ BlobLayout blob_layout(const unsigned char* p, size_t n) {
   std::memcpy(&vb, p + 24, 4);
   std::memcpy(&W, p + 28, 4);
   if (ncomp < 1 || ncomp > ISR_MAX_COMP || ne < 1 || (vb != 4 && vb != 8) || W < 1) return L;
-  const size_t off = 56 + 64 * (size_t)ncomp + (size_t)ncomp * ne * W * 8 + (size_t)ncomp * (ne + 1) * 8;
+  const size_t off = 64 + 72 * (size_t)ncomp + (size_t)ncomp * ne * W * 8 + (size_t)ncomp * (ne + 1) * 8;
   if (off > n || (n - off) % vb) return L;
   L.values_off = off;
   L.values_bytes = n - off;

@@ -763,6 +763,8 @@ __global__ __launch_bounds__(Shape<N>::THREADS) void k_decompress(Job j, void* o
           rank += (u32)__popcll(word & ((1ull << (f & 63)) - 1ull));
           cm[r] = j.vbytes == 8 ? ((const double*)j.values)[base + rank]
                                 : (double)((const float*)j.values)[base + rank];
+          // quantisation codes: the value is (code * step) / sqrt(g3)
+          if (j.qstep) cm[r] = (cm[r] * j.qstep[comp]) / __builtin_sqrt(j.tab.g3[f]);
         }
       }
     }
@@ -778,6 +780,115 @@ __global__ __launch_bounds__(Shape<N>::THREADS) void k_decompress(Job j, void* o
       }
     }
   }
+}
+
+// ---- quantised variant: codes of the kept values and the error they leave ------
+// Per tile: every kept FP64 coefficient c of the blob gets the code
+// q = rint((c sqrt(g3)) / step), written as an FP32 integer at the value's
+// position; the dequantised (q step) / sqrt(g3) go through the fixed-order
+// FP64 inverse (the one decompression uses), and the terms w3 (u - u~)^2 into
+// the exact error histogram j.histR.  A code of magnitude 2^24 or more sets
+// j.ticket[1].  Unit Jacobians.
+template <int N>
+struct QuantLds {
+  typedef Shape<N> S;
+  double su[S::TILE];
+  double sw[S::TILE];
+  typename Xf64<N>::Smem sm;
+  LdsHist hR;
+  u64 bm[S::EPI * S::W];
+};
+
+template <int N>
+__global__ __launch_bounds__(Shape<N>::THREADS) void k_quantize(Job j) {
+  typedef Shape<N> S;
+  typedef Xf64<N> X;
+  constexpr int n = S::n, n2 = S::n2, n3 = S::n3, EPI = S::EPI, T = S::THREADS, W = S::W;
+  __shared__ QuantLds<N> L;
+  typename X::Regs rg;
+  const int tid = threadIdx.x;
+  const int el = tid / n2, a = (tid % n2) / n, b = tid % n;
+  const long long E = j.n_elem, tiles = (E + EPI - 1) / EPI, total = tiles * j.ncomp;
+  lh_init(L.hR, tid, T);
+  X::init(L.sm, rg, j.tab, tid, T);
+  int cur = -1;
+  bool first = true;
+  for (long long tk = blockIdx.x; tk < total; tk += gridDim.x) {
+    const int comp = (int)(tk / tiles);
+    if (comp != cur) {
+      if (cur >= 0) {
+        __syncthreads();
+        lh_flush(L.hR, j.histR + (size_t)cur * HBINS, tid, T);
+        __syncthreads();
+        lh_init(L.hR, tid, T);
+      }
+      cur = comp;
+      first = true;
+    }
+    const long long e0 = (tk % tiles) * EPI;
+    const int ne = (int)((E - e0) < EPI ? (E - e0) : EPI);
+    __syncthreads();
+    {
+      Prefetch<T, S::TILE> pf;
+      pf.load(j.u + (size_t)comp * j.comp_stride + e0 * n3, ne * n3, tid);
+      pf.store(L.su, ne * n3, tid);
+    }
+    const u64* gbm = j.bitmap + ((size_t)comp * E + e0) * W;
+    for (int k = tid; k < EPI * W; k += T) L.bm[k] = k < ne * W ? gbm[k] : 0ull;
+    __syncthreads();
+    const bool act = tid < S::ACT && el < ne;
+    const double step = j.qstep[comp];
+    double cm[n], ut[n];
+#pragma unroll
+    for (int r = 0; r < n; ++r) cm[r] = 0.0;
+    if (act) {
+      const u64 base = j.voff[comp] + j.elem_ptr[(size_t)comp * (E + 1) + e0 + el];
+#pragma unroll
+      for (int r = 0; r < n; ++r) {
+        const int f = (r * n + a) * n + b;
+        const int wi = f >> 6;
+        const u64 word = L.bm[el * W + wi];
+        if ((word >> (f & 63)) & 1ull) {
+          u32 rank = 0;
+          for (int w = 0; w < wi; ++w) rank += (u32)__popcll(L.bm[el * W + w]);
+          rank += (u32)__popcll(word & ((1ull << (f & 63)) - 1ull));
+          const double c = ((const double*)j.values)[base + rank];
+          const double sq = __builtin_sqrt(j.tab.g3[f]);
+          const double q = __builtin_rint((c * sq) / step);
+          if (!(__builtin_fabs(q) < 16777216.0)) atomicOr(&j.ticket[1], 1u);
+          j.qvals[base + rank] = (float)q;
+          cm[r] = (q * step) / sq;
+        }
+      }
+    }
+    X::inverse(L.sw, L.sm, rg, el, a, b, act, ne, cm, ut);
+    double et[n];
+    if (act) {
+      const double* w3 = j.tab.w3 + (a * n + b) * n;
+      const double* pu = L.su + el * n3 + (a * n + b) * n;
+#pragma unroll
+      for (int i = 0; i < n; ++i) {
+        const double d = pu[i] - ut[i];
+        et[i] = w3[i] * (d * d);
+      }
+    }
+    if (first) {
+      if (act) {
+#pragma unroll
+        for (int i = 0; i < n; ++i) lh_note_max(L.hR, et[i]);
+      }
+      __syncthreads();
+      if (tid == 0) lh_place(L.hR);
+      __syncthreads();
+      first = false;
+    }
+    if (act) {
+#pragma unroll
+      for (int i = 0; i < n; ++i) lh_insert(L.hR, j.histR + (size_t)comp * HBINS, et[i]);
+    }
+  }
+  __syncthreads();
+  if (cur >= 0) lh_flush(L.hR, j.histR + (size_t)cur * HBINS, tid, T);
 }
 
 // ---- forward transform only -----------------------------------------------------
@@ -850,6 +961,8 @@ hipError_t launch_pass_prec(int kind, const Job& j, int grid, hipStream_t s, voi
       hipLaunchKernelGGL((k_forward<NN, PREC>), dim3(grid), blk, 0, s, j, extra);                                 \
     else if (kind == K_DECOMP)                                                                                    \
       hipLaunchKernelGGL((k_decompress<NN, PREC>), dim3(grid), blk, 0, s, j, extra, extra_i);                     \
+    else if (kind == K_QUANT && PREC == P_FP64)                                                                   \
+      hipLaunchKernelGGL((k_quantize<NN>), dim3(grid), blk, 0, s, j);                                             \
     else                                                                                                          \
       return hipErrorInvalidValue;                                                                                \
     break;                                                                                                        \

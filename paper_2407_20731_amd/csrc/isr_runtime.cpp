@@ -210,21 +210,24 @@ struct isr_blob {
   size_t dev_bytes = 0;
   int order = 0, ncomp = 0, vbytes = 8, W = 0, precision = 0, status = 0;
   int engine = 0, tile = 0;  // FP32 / BF16: the engine (and dense tile) whose inverse decompresses it
+  int value_kind = 0;        // 0: coefficient values; 1: quantisation codes (integers held by FP32)
   int64_t n_elem = 0;
   double tol = 0;
   struct Hdr {
     double U2, B, tau, dropped, err2, rel;
     uint64_t kept, voff;
+    double qstep;  // quantisation step of the codes (value_kind 1), else 0
   } comp[ISR_MAX_COMP];
   uint64_t total_kept = 0;
   u64* voff() const { return (u64*)dev; }
+  double* qstep_dev() const { return (double*)((char*)dev + 64); }  // device copy of the steps
   u64* bitmap() const { return (u64*)((char*)dev + 256); }
   size_t bitmap_bytes() const { return (size_t)ncomp * n_elem * W * 8; }
   u64* elem_ptr() const { return (u64*)((char*)bitmap() + bitmap_bytes()); }
   size_t ptr_bytes() const { return (size_t)ncomp * (n_elem + 1) * 8; }
   void* values() const { return (char*)elem_ptr() + ptr_bytes(); }
   size_t values_bytes() const { return (size_t)total_kept * vbytes; }
-  static constexpr size_t HDR = 56, CHDR = 64;
+  static constexpr size_t HDR = 64, CHDR = 72;
   size_t serialized() const { return HDR + CHDR * ncomp + bitmap_bytes() + ptr_bytes() + values_bytes(); }
 };
 
@@ -395,6 +398,7 @@ static Job make_job(isr_ctx* c, const isr_field* f, const Sizes& z, char* scratc
   j.precision = f->precision;
   j.vbytes = z.vbytes;
   j.tol = f->tol;
+  j.cut_scale = 1.0;
   for (int k = 0; k < 8; ++k) j.Bov[k] = -1.0;
   j.tab = c->tab[f->order];
   j.histE = (HistBin*)(scratch + z.off_histE);
@@ -723,6 +727,7 @@ int task_begin(isr_ctx* c, const isr_field* f, hipStream_t s, bool timing, Task*
     return fail(ISR_EDEVICE, "could not create host state or event");
   }
   t->j = make_job(c, f, t->z, t->scratch, blob_ptrs(t->b));
+  t->j.cut_scale = t->cut_scale;
   t->fast = t->z.fast;
   t->timing = timing;
   if (timing)
@@ -1256,9 +1261,10 @@ int run_batch(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_s
 }
 
 // Run one compression to completion on the caller's stream.
-int run_compress(isr_ctx* c, const isr_field* f, isr_blob** out, isr_stats* st) {
+int run_compress(isr_ctx* c, const isr_field* f, isr_blob** out, isr_stats* st, double cut_scale) {
   *out = nullptr;
   Task t;
+  t.cut_scale = cut_scale;
   int rc = task_begin(c, f, (hipStream_t)f->stream, (c->flags & ISR_FLAG_TIMING) && st, &t);
   if (rc) return rc;
   for (;;) {
@@ -1485,6 +1491,7 @@ int isr_decompress(isr_ctx* c, const isr_blob* b, void* d_out, int32_t out_prec,
   j.elem_ptr = b->elem_ptr();
   j.values = b->values();
   j.voff = b->voff();
+  if (b->value_kind == 1) j.qstep = b->qstep_dev();  // quantisation codes
   const int ofp64 = out_prec == ISR_PREC_FP64;
   hipStream_t s = (hipStream_t)stream;
   if (b->engine == ENG_GENERAL) {
@@ -1551,7 +1558,7 @@ int isr_blob_size(const isr_blob* b, uint64_t* bytes) {
 
 static void put_hdr(const isr_blob* b, char* p) {
   std::memcpy(p, "ISR1", 4);
-  uint32_t ver = 2;
+  uint32_t ver = 3;
   std::memcpy(p + 4, &ver, 4);
   int32_t v32 = b->order;
   std::memcpy(p + 8, &v32, 4);
@@ -1572,6 +1579,10 @@ static void put_hdr(const isr_blob* b, char* p) {
   std::memcpy(p + 48, &v32, 4);
   v32 = b->tile;
   std::memcpy(p + 52, &v32, 4);
+  v32 = b->value_kind;
+  std::memcpy(p + 56, &v32, 4);
+  v32 = 0;
+  std::memcpy(p + 60, &v32, 4);
   for (int k = 0; k < b->ncomp; ++k) std::memcpy(p + isr_blob::HDR + isr_blob::CHDR * k, &b->comp[k], isr_blob::CHDR);
 }
 
@@ -1618,10 +1629,14 @@ int isr_blob_from_host(isr_ctx* c, const void* buf, uint64_t nbytes, isr_blob** 
   b->engine = v32;
   std::memcpy(&v32, p + 52, 4);
   b->tile = v32;
-  if (ver != 2) return fail(ISR_EINVAL, "blob version %u is not 2", ver);
+  std::memcpy(&v32, p + 56, 4);
+  b->value_kind = v32;
+  if (ver != 3) return fail(ISR_EINVAL, "blob version %u is not 3", ver);
+  if (b->value_kind != 0 && !(b->value_kind == 1 && b->vbytes == 4 && b->precision == ISR_PREC_FP64))
+    return fail(ISR_EINVAL, "corrupt blob header (value kind %d)", b->value_kind);
   if (b->order < 1 || b->order > ISR_MAX_ORDER || b->ncomp < 1 || b->ncomp > ISR_MAX_COMP || b->n_elem < 1 ||
       (b->vbytes != 4 && b->vbytes != 8) || b->W != words_per_elem(b->order) ||
-      (b->vbytes == 8) != (b->precision == ISR_PREC_FP64) ||
+      (b->vbytes == 8) != (b->precision == ISR_PREC_FP64 && b->value_kind == 0) ||
       (b->precision != ISR_PREC_FP64 && b->precision != ISR_PREC_FP32 && b->precision != ISR_PREC_BF16))
     return fail(ISR_EINVAL, "corrupt blob header");
   if ((b->engine == ENG_GENERAL && b->tile != 0) ||
@@ -1664,7 +1679,10 @@ int isr_blob_from_host(isr_ctx* c, const void* buf, uint64_t nbytes, isr_blob** 
   u64 vo[ISR_MAX_COMP];
   for (int k = 0; k < b->ncomp; ++k) vo[k] = b->comp[k].voff;
   const size_t hb = isr_blob::HDR + isr_blob::CHDR * b->ncomp;
-  if (hipMemcpy(b->voff(), vo, 8 * b->ncomp, hipMemcpyHostToDevice) != hipSuccess ||
+  double qs[ISR_MAX_COMP];
+  for (int k = 0; k < b->ncomp; ++k) qs[k] = b->comp[k].qstep;
+  if (hipMemcpy(b->qstep_dev(), qs, 8 * b->ncomp, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->voff(), vo, 8 * b->ncomp, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b->bitmap(), p + hb, nbytes - hb, hipMemcpyHostToDevice) != hipSuccess) {
     c->arena->free(b->dev);
     return fail(ISR_EDEVICE, "blob upload failed");
@@ -1807,3 +1825,160 @@ int run_compress_noalloc(isr_ctx* c, const isr_field* f, char* scratch, size_t s
 }
 
 }  // namespace isr
+
+// ---------------------------------------------------------------------------
+// quantised variant (isr_compress_quantized)
+
+namespace isr {
+
+// The cut of the plain FP64 method at ((tol*tol)*U2)*(1 - share), then the
+// kept coefficients quantised with the step 2 sqrt((B - S_c)/K)(1 - 2^-20)
+// that the rest of the budget B = (tol*tol)*U2 allows, the exact error of the
+// dequantised field measured, and the step shrunk by (tol/rel)(1 - 2^-20)
+// while rounding leaves it above tol (at most 4 times).
+int run_compress_quantized(isr_ctx* c, const isr_field* f, double share, isr_blob** out, isr_stats* st) {
+  *out = nullptr;
+  int rc = check_field(f);
+  if (rc) return rc;
+  if (f->precision != ISR_PREC_FP64) return fail(ISR_EINVAL, "the quantised variant runs on the FP64 path");
+  if (f->elem_jac) return fail(ISR_EINVAL, "the quantised variant takes unit Jacobians (elem_jac NULL)");
+  if (!(f->tol >= 0.0)) return fail(ISR_EINVAL, "the quantised variant needs tol >= 0");
+  if (!(share >= 0.0 && share < 1.0)) return fail(ISR_EINVAL, "share must be in [0, 1)");
+  const double t0 = now_s();
+  isr_blob* b = nullptr;
+  isr_stats s0;
+  rc = run_compress(c, f, &b, &s0, 1.0 - share);
+  if (rc != ISR_OK) {
+    if (b) isr_blob_free(b);
+    return rc;
+  }
+  const int nc = f->ncomp;
+  hipStream_t s = (hipStream_t)f->stream;
+  double delta[ISR_MAX_COMP], Bf[ISR_MAX_COMP], err2[ISR_MAX_COMP], rel[ISR_MAX_COMP];
+  for (int k = 0; k < nc; ++k) {
+    Bf[k] = (f->tol * f->tol) * b->comp[k].U2;
+    const uint64_t K = b->comp[k].kept;
+    delta[k] = K ? (2.0 * std::sqrt((Bf[k] - b->comp[k].dropped) / (double)K)) * (1.0 - 0x1p-20) : 0.0;
+  }
+  // the quantised blob: the cut's bitmaps and offsets, FP32 codes
+  isr_blob* q = new isr_blob();
+  *q = *b;
+  q->vbytes = 4;
+  q->value_kind = 1;
+  q->engine = ENG_GENERAL;
+  q->tile = 0;
+  q->dev_bytes = 256 + q->bitmap_bytes() + q->ptr_bytes() + q->values_bytes();
+  q->dev = c->arena->alloc(q->dev_bytes, true);
+  const size_t hist_bytes = (size_t)nc * HBINS * sizeof(HistBin);
+  char* scr = (char*)c->arena->alloc(hist_bytes + 512);
+  auto cleanup = [&]() {
+    if (scr) c->arena->free(scr);
+    isr_blob_free(b);
+  };
+  if (!q->dev || !scr) {
+    if (q->dev) c->arena->free(q->dev);
+    delete q;
+    cleanup();
+    return fail(ISR_ENOMEM, "the quantised blob does not fit the HBM budget");
+  }
+  Job j;
+  std::memset(&j, 0, sizeof(j));
+  const long long n = f->order + 1, n3 = n * n * n;
+  j.u = f->field;
+  j.comp_stride = f->comp_stride ? f->comp_stride : f->n_elem * n3;
+  j.n_elem = f->n_elem;
+  j.order = f->order;
+  j.ncomp = nc;
+  j.precision = ISR_PREC_FP64;
+  j.vbytes = 8;
+  j.tab = c->tab[f->order];
+  j.bitmap = b->bitmap();
+  j.elem_ptr = b->elem_ptr();
+  j.values = b->values();
+  j.voff = b->voff();
+  j.qstep = q->qstep_dev();
+  j.qvals = (float*)q->values();
+  j.histR = (HistBin*)scr;
+  j.ticket = (u32*)(scr + hist_bytes);
+  double* err_dev = (double*)(scr + hist_bytes + 256);
+  const long long total = (long long)tiles_per_comp(f->order, f->n_elem) * nc;
+  const int grid = (int)std::min<long long>(total, (long long)c->num_cu * resident_blocks(K_PASS3, ISR_PREC_FP64, f->order));
+  int iters = 0;
+  for (;;) {
+    uint32_t over = 0;
+    rc = ISR_OK;
+    if (launch_zero(scr, hist_bytes + 256, s) != hipSuccess ||
+        hipMemcpyAsync((void*)j.qstep, delta, 8 * nc, hipMemcpyHostToDevice, s) != hipSuccess ||
+        launch_pass(K_QUANT, ISR_PREC_FP64, j, grid, s) != hipSuccess || launch_err_total(j, err_dev, s) != hipSuccess ||
+        hipMemcpyAsync(err2, err_dev, 8 * nc, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&over, j.ticket + 1, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      rc = fail(ISR_EDEVICE, "quantisation pass failed: %s", hipGetErrorString(hipGetLastError()));
+    if (!rc && over) rc = fail(ISR_ETOL, "a quantisation code needs more than 24 bits at this step");
+    if (rc) {
+      c->arena->free(q->dev);
+      delete q;
+      cleanup();
+      return rc;
+    }
+    bool again = false;
+    for (int k = 0; k < nc; ++k) {
+      rel[k] = q->comp[k].U2 > 0.0 ? std::sqrt(err2[k] / q->comp[k].U2) : 0.0;
+      if (rel[k] > f->tol && iters < 4) {
+        delta[k] = (delta[k] * (f->tol / rel[k])) * (1.0 - 0x1p-20);
+        again = true;
+      }
+    }
+    if (!again) break;
+    ++iters;
+  }
+  // the blob's bitmaps, offsets and value offsets are the cut's
+  if (hipMemcpyAsync(q->voff(), b->voff(), 64, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(q->bitmap(), b->bitmap(), q->bitmap_bytes() + q->ptr_bytes(), hipMemcpyDeviceToDevice, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    c->arena->free(q->dev);
+    delete q;
+    cleanup();
+    return fail(ISR_EDEVICE, "quantised blob copy failed");
+  }
+  bool within = true;
+  for (int k = 0; k < nc; ++k) {
+    q->comp[k].B = Bf[k];
+    q->comp[k].err2 = err2[k];
+    q->comp[k].rel = rel[k];
+    q->comp[k].qstep = delta[k];
+    within = within && !(rel[k] > f->tol);
+  }
+  q->status = within ? ISR_OK : ISR_ETOL;
+  cleanup();
+  if (st) {
+    *st = s0;
+    for (int k = 0; k < nc; ++k) {
+      st->budget[k] = Bf[k];
+      st->err2[k] = err2[k];
+      st->rel_err[k] = rel[k];
+    }
+    st->blob_bytes = q->serialized();
+    st->cr = st->in_bytes ? (double)((int64_t)st->in_bytes - (int64_t)st->blob_bytes) / (double)st->in_bytes : 0.0;
+    st->repair_iters = iters;
+    st->status = q->status;
+    st->t_submit = t0;
+    st->t_done = now_s();
+  }
+  *out = q;
+  if (!within) fail(ISR_ETOL, "relative error above tol after %d step repairs", iters);
+  return q->status;
+}
+
+}  // namespace isr
+
+extern "C" int isr_compress_quantized(isr_ctx* c, const isr_field* f, double share, isr_blob** out, isr_stats* st) {
+  if (!c || !out) return fail(ISR_EINVAL, "ctx or out is NULL");
+  *out = nullptr;
+  if (st) std::memset(st, 0, sizeof(*st));
+  int rc = set_device(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> g(c->mu);
+  return isr::run_compress_quantized(c, f, share, out, st);
+}

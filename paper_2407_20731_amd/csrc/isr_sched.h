@@ -70,7 +70,8 @@ Sizes plan_sizes(const isr_field* f, int tile);
 int ctx_tile(const isr_ctx* c, int order, int precision);
 
 int enqueue_pipeline(isr_ctx* c, const Job& j, const Sizes& z, hipStream_t s, hipEvent_t* ev, bool fast);
-int run_compress(isr_ctx* c, const isr_field* f, isr_blob** out, isr_stats* st);
+int run_compress(isr_ctx* c, const isr_field* f, isr_blob** out, isr_stats* st, double cut_scale = 1.0);
+int run_compress_quantized(isr_ctx* c, const isr_field* f, double share, isr_blob** out, isr_stats* st);
 int run_batch(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_stats* st);
 int run_batch_sequential(isr_ctx* c, const isr_field* fs, int count, isr_blob** outs, isr_stats* st);
 uint64_t request_footprint(const isr_field* f);
@@ -97,6 +98,7 @@ uint64_t ctx_budget(const isr_ctx* c);
 // One compression in flight: its allocations, job, stream and completion event.
 struct Task {
   isr_ctx* c = nullptr;
+  double cut_scale = 1.0;  // the cut's share of the budget (quantised variant)
   isr_field f;
   Sizes z;
   char* scratch = nullptr;

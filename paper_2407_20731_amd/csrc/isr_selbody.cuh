@@ -53,6 +53,7 @@ DEV void select1_body(const Job& j, int comp, int sample) {
     return;
   }
   double B = (tol * tol) * U2;
+  if (j.cut_scale != 1.0) B = B * j.cut_scale;  // a share of the budget left to a later stage
   // MFMA paths: the measured error differs from the dropped energy by the
   // transform error (about 1e-5 relative in FP32-split BF16 at tol 1e-3), so
   // they select against a budget that much smaller and rarely need a repair

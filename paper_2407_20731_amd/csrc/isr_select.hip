@@ -30,6 +30,16 @@ hipError_t launch_state_out(const CompState* src, CompState* host_dst, int ncomp
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(64) void k_err_total(Job j, double* err2_out) {
+  const double e = wb_round(hist_total(j.histR + (size_t)blockIdx.x * HBINS));
+  if (threadIdx.x == 0) err2_out[blockIdx.x] = e;
+}
+
+hipError_t launch_err_total(const Job& j, double* err2_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_err_total, dim3(j.ncomp), dim3(64), 0, s, j, err2_out);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   size_t nw = bytes / 8;
   if (nw == 0) return hipSuccess;

@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "isr_compress": (I32, [P, C.POINTER(isr_field), C.POINTER(P), C.POINTER(isr_stats)]),
         "isr_compress_batch": (I32, [P, C.POINTER(isr_field), I32, C.POINTER(P), C.POINTER(isr_stats)]),
         "isr_compress_noalloc": (I32, [P, C.POINTER(isr_field), P, U64, C.POINTER(U64), C.POINTER(isr_stats)]),
+        "isr_compress_quantized": (I32, [P, C.POINTER(isr_field), C.c_double, C.POINTER(P), C.POINTER(isr_stats)]),
         "isr_submit": (I32, [P, C.POINTER(isr_field), C.POINTER(U64)]),
         "isr_poll": (I32, [P, U64, I32, C.POINTER(P), C.POINTER(isr_stats)]),
         "isr_decompress": (I32, [P, P, P, I32, P]),
@@ -193,7 +194,8 @@ class BlobArrays:
     status: int
     engine: int                # FP32 / BF16: engine whose inverse decompresses it (0 general, 1 wave-tile, 2 dense)
     tile: int                  # its dense tile (engine 2)
-    comps: List[dict]          # U2, B, tau, dropped, err2, rel_err, kept, voff
+    value_kind: int            # 0 coefficient values, 1 quantisation codes (qstep per component)
+    comps: List[dict]          # U2, B, tau, dropped, err2, rel_err, kept, voff, qstep
     bitmap: np.ndarray         # uint64 [ncomp, n_elem, W]
     elem_ptr: np.ndarray       # uint64 [ncomp, n_elem + 1]
     values: List[np.ndarray]   # per component
@@ -204,15 +206,16 @@ def parse_blob(buf: bytes) -> BlobArrays:
     if buf[:4] != b"ISR1":
         raise ValueError("not an ISR1 blob")
     version, = struct.unpack_from("<I", buf, 4)
-    if version != 2:
-        raise ValueError(f"blob version {version} is not 2")
-    order, ncomp, n_elem, vb, W, tol, prec, status, engine, tile = struct.unpack_from("<iiqiidiiii", buf, 8)
+    if version != 3:
+        raise ValueError(f"blob version {version} is not 3")
+    order, ncomp, n_elem, vb, W, tol, prec, status, engine, tile, kind = struct.unpack_from("<iiqiidiiiii", buf, 8)
     comps = []
-    off = 56
+    off = 64
     for _ in range(ncomp):
-        U2, B, tau, dropped, err2, rel, kept, voff = struct.unpack_from("<6d2Q", buf, off)
-        comps.append(dict(U2=U2, B=B, tau=tau, dropped=dropped, err2=err2, rel_err=rel, kept=kept, voff=voff))
-        off += 64
+        U2, B, tau, dropped, err2, rel, kept, voff, qstep = struct.unpack_from("<6d2Qd", buf, off)
+        comps.append(dict(U2=U2, B=B, tau=tau, dropped=dropped, err2=err2, rel_err=rel, kept=kept, voff=voff,
+                          qstep=qstep))
+        off += 72
     nb = ncomp * n_elem * W
     bitmap = np.frombuffer(buf, dtype="<u8", count=nb, offset=off).reshape(ncomp, n_elem, W)
     off += 8 * nb
@@ -223,7 +226,8 @@ def parse_blob(buf: bytes) -> BlobArrays:
     values = []
     for c in comps:
         values.append(np.frombuffer(buf, dtype=vdt, count=c["kept"], offset=off + c["voff"] * vb))
-    return BlobArrays(order, ncomp, n_elem, vb, W, tol, prec, status, engine, tile, comps, bitmap, elem_ptr, values)
+    return BlobArrays(order, ncomp, n_elem, vb, W, tol, prec, status, engine, tile, kind, comps, bitmap, elem_ptr,
+                      values)
 
 
 class Blob:
@@ -360,6 +364,17 @@ class Context:
         rc = load_library().isr_compress(self._h, C.byref(f), C.byref(h), C.byref(st))
         if rc not in (OK, ETOL):
             _check(rc, "isr_compress")
+        return Blob(self, h.value, _stats_dict(st, f.ncomp), rc)
+
+    def compress_quantized(self, u, order: int, tol: float, share: float = 0.5, stream=None) -> Blob:
+        """Quantised variant (FP64 path): cut at (1 - share) of the budget,
+        kept coefficients coded as integers with the rest of it."""
+        f = self._field(u, order, tol, "fp64", None, stream)
+        h = C.c_void_p()
+        st = isr_stats()
+        rc = load_library().isr_compress_quantized(self._h, C.byref(f), float(share), C.byref(h), C.byref(st))
+        if rc not in (OK, ETOL):
+            _check(rc, "isr_compress_quantized")
         return Blob(self, h.value, _stats_dict(st, f.ncomp), rc)
 
     def compress_noalloc(self, u, order: int, tol: float, out, precision="fp64", stream=None):

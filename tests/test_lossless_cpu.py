@@ -23,7 +23,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libisr.so not b
 
 
 def serialized_blob(u, order, tol, value_dtype=np.float32):
-    """A blob in the serialized layout (version 2) from the oracle's result,
+    """A blob in the serialized layout (version 3) from the oracle's result,
     values stored as value_dtype."""
     ref = oracle.compress(u, order, tol)
     n = order + 1
@@ -31,10 +31,10 @@ def serialized_blob(u, order, tol, value_dtype=np.float32):
     W = (n ** 3 + 63) // 64
     vb = np.dtype(value_dtype).itemsize
     prec = 0 if vb == 8 else 1
-    out = [b"ISR1", struct.pack("<Iiiqiidiiii", 2, order, len(ref.comps), E, vb, W, tol, prec, 0, 0, 0)]
+    out = [b"ISR1", struct.pack("<Iiiqiidiiiiii", 3, order, len(ref.comps), E, vb, W, tol, prec, 0, 0, 0, 0, 0)]
     voff = 0
     for rc in ref.comps:
-        out.append(struct.pack("<6d2Q", rc.U2, rc.B, rc.tau, rc.dropped, rc.err2, rc.rel_err, rc.kept, voff))
+        out.append(struct.pack("<6d2Qd", rc.U2, rc.B, rc.tau, rc.dropped, rc.err2, rc.rel_err, rc.kept, voff, 0.0))
         voff += rc.kept
     for rc in ref.comps:
         out.append(rc.bitmap.astype("<u8").tobytes())
@@ -43,7 +43,7 @@ def serialized_blob(u, order, tol, value_dtype=np.float32):
     for rc in ref.comps:
         out.append(rc.values.astype(value_dtype).tobytes())
     blob = b"".join(out)
-    assert len(blob) == 56 + 64 * len(ref.comps) + 8 * len(ref.comps) * E * W + 8 * len(ref.comps) * (E + 1) + voff * vb
+    assert len(blob) == 64 + 72 * len(ref.comps) + 8 * len(ref.comps) * E * W + 8 * len(ref.comps) * (E + 1) + voff * vb
     return blob, u.nbytes
 
 

@@ -21,7 +21,7 @@ torch = pytest.importorskip("torch")
 def _worst_case_bytes(E, order, ncomp, vbytes):
     n = order + 1
     W = (n ** 3 + 63) // 64
-    return 56 + 64 * ncomp + 8 * ncomp * E * W + 8 * ncomp * (E + 1) + ncomp * E * n ** 3 * vbytes
+    return 64 + 72 * ncomp + 8 * ncomp * E * W + 8 * ncomp * (E + 1) + ncomp * E * n ** 3 * vbytes
 
 
 @pytest.mark.parametrize("prec", ["fp64", "bf16"])
