@@ -26,6 +26,8 @@ relative L2 error bound -- as one data-parallel pass over the elements:
   * ``quantize``  a variant of the lossy step: the cut at a share of the
                   budget, then JPEG-like uniform quantisation of the kept
                   coefficients in the energy norm with the rest of it.
+  * ``elemcut``   a variant of the selection: every element cut alone by the
+                  plain value rule at its own share of the budget.
 
 Pins (what each function is checked against, in ``tests/test_oracle_*.py``):
 closed-form GLL rules, scipy's Gauss-Jacobi roots, quadrature exactness,
@@ -36,8 +38,10 @@ math.fsum / Fraction sums, brute force over all subsets on tiny inputs,
 hand-computed repair budgets and a repair run to its cap, bitmap words
 written out by hand for known kept sets, and for the quantised variant its
 step against hand values, the per-coefficient error bound on random data and
-Parseval with independently summed coefficient-space errors.  Every
-function has such a pin.
+Parseval with independently summed coefficient-space errors; for the
+per-element cut brute force over every subset of tiny elements, each
+element equal to the plain method run on it alone, the bound per element and
+the repair of the budget scale.  Every function has such a pin.
 """
 
 from .tables import gll_tables, Tables  # noqa: F401
