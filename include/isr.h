@@ -232,6 +232,22 @@ int isr_compress_noalloc(isr_ctx *ctx, const isr_field *f, void *d_out, uint64_t
  * than 24 bits. */
 int isr_compress_quantized(isr_ctx *ctx, const isr_field *f, double share, isr_blob **out, isr_stats *st);
 
+/* Per-element cut, a variant of the selection (Sec. IV-B: the lossy step's
+ * sorting kernels, read as a selection made element by element).  FP64
+ * path, f->tol >= 0, Jacobians allowed, n_elem < 2^32.  Every element e of a
+ * component is cut alone by the plain value rule: U2_e = RN(exact sum of its
+ * norm terms), budget B_e = ((tol*tol)*U2_e)*s, threshold tau_e = the largest
+ * of its energies v (or +inf) with RN(exact sum of its energies below v) <= B_e;
+ * kept = energies >= tau_e.  U2, err2 and the dropped energy are the exact
+ * component totals as in isr_compress, B = (tol*tol)*U2, and the blob's tau
+ * is NaN (the thresholds are per element).  While rounding leaves rel above
+ * tol, s <- (s*((tol/rel)*(tol/rel)))*(1 - 2^-20), at most 4 times; then
+ * ISR_ETOL.  Each element then keeps its own relative error within tol, up
+ * to rounding, at the price of more kept coefficients than the global cut.
+ * The blob has the layout of isr_compress's FP64 blobs.  Errors: as
+ * isr_compress; ISR_EINVAL for another precision or a negative tol. */
+int isr_compress_elemcut(isr_ctx *ctx, const isr_field *f, isr_blob **out, isr_stats *st);
+
 /* Compress several snapshots (orders may differ) in one batched launch
  * sequence.  FP64 snapshots of orders 5, 7 and 9: one persistent launch of
  * the general passes.  FP32 / BF16: one streaming pipeline per snapshot on

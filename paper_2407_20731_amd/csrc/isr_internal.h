@@ -136,6 +136,9 @@ struct Job {
   // codes written by the quantisation pass (FP32 integers, values' layout)
   const double* qstep;
   float* qvals;
+  // per-element cut: the threshold of every element ([ncomp][n_elem]); null
+  // = the component's threshold st[comp].tau
+  const double* tau_elem;
 };
 
 // Persistent batch launch (isr_batch.cuh): phases of the shared work queue.
@@ -191,6 +194,14 @@ hipError_t launch_state_out(const CompState* src, CompState* host_dst, int ncomp
 // correctly rounded exact totals of the error histograms j.histR, per
 // component, into err2_out[ncomp] (device)
 hipError_t launch_err_total(const Job& j, double* err2_out, hipStream_t s);
+// per-element cut (isr_elemcut.hip): every element's threshold into
+// tau[ncomp][n_elem] from the FP64 coefficients coef (isr_forward's layout),
+// at budgets ((tol*tol)*U2_e)*scale[comp]; the component totals (U2, the
+// dropped energy) and kept counts into j.st.  G: zeroed digit totals of
+// elemcut_digit_bytes(ncomp) bytes; j.st[*].kept and flags start at 0.
+hipError_t launch_elemcut(const Job& j, const double* coef, double* tau, u64* G, const double* scale, int grid,
+                          hipStream_t s);
+size_t elemcut_digit_bytes(int ncomp);
 hipError_t launch_select1(const Job& j, int sample, hipStream_t s);
 hipError_t launch_refine(const Job& j, int level, int grid_x, hipStream_t s);
 hipError_t launch_select(const Job& j, int level, hipStream_t s);

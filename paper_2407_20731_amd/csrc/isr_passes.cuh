@@ -570,7 +570,7 @@ DEV void pass3_tile(const Job& j, int comp, long long t, Pass3Lds<N, PREC>& L,
   const int el = tid / n2, a = (tid % n2) / n, b = tid % n;
   const long long E = j.n_elem;
   const long long tiles = (E + EPI - 1) / EPI;
-  const double tau = j.st[comp].tau;
+  const double tau_c = j.st[comp].tau;
   const long long e0 = t * EPI;
   const int ne = (int)((E - e0) < EPI ? (E - e0) : EPI);
   const double* u = j.u + (size_t)comp * j.comp_stride;
@@ -587,6 +587,7 @@ DEV void pass3_tile(const Job& j, int comp, long long t, Pass3Lds<N, PREC>& L,
   bool keep[n];
   X::forward(L.su, L.sw, L.sm, rg, el, a, b, act, ne, c);
   if (act) {
+    const double tau = j.tau_elem ? j.tau_elem[(size_t)comp * E + e] : tau_c;
 #pragma unroll
     for (int r = 0; r < n; ++r) {
       const double en = jw(j.jac, e, j.tab.g3[(r * n + a) * n + b]) * (c[r] * c[r]);

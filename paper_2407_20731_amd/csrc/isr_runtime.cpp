@@ -1792,6 +1792,7 @@ int run_compress_noalloc(isr_ctx* c, const isr_field* f, char* scratch, size_t s
   // describe the result in a blob record on the stack (no device memory of
   // its own) to form the header
   isr_blob b;
+  std::memset(b.comp, 0, sizeof(b.comp));  // records not set below (the quantisation step) stay 0
   b.ctx = c;
   b.order = f->order;
   b.ncomp = nc;
@@ -1971,6 +1972,133 @@ int run_compress_quantized(isr_ctx* c, const isr_field* f, double share, isr_blo
   return q->status;
 }
 
+
+// Per-element cut: every element cut alone at ((tol*tol)*U2_e)*s_c; pass 3
+// of the general pipeline compacts, inverts and measures the exact error;
+// s_c follows the plain budget repair while rounding leaves rel above tol.
+int run_compress_elemcut(isr_ctx* c, const isr_field* f, isr_blob** out, isr_stats* st) {
+  *out = nullptr;
+  int rc = check_field(f);
+  if (rc) return rc;
+  if (f->precision != ISR_PREC_FP64) return fail(ISR_EINVAL, "the per-element cut runs on the FP64 path");
+  if (!(f->tol >= 0.0)) return fail(ISR_EINVAL, "the per-element cut needs tol >= 0");
+  if (f->n_elem >= (1ll << 32)) return fail(ISR_EINVAL, "the per-element cut takes fewer than 2^32 elements");
+  const double t0 = now_s();
+  const int nc = f->ncomp;
+  const long long n = f->order + 1, n3 = n * n * n, E = f->n_elem;
+  const int W = (int)((n3 + 63) / 64);
+  hipStream_t s = (hipStream_t)f->stream;
+  isr_blob* b = new isr_blob();
+  b->ctx = c;
+  b->order = f->order;
+  b->ncomp = nc;
+  b->n_elem = E;
+  b->vbytes = 8;
+  b->W = W;
+  b->tol = f->tol;
+  b->precision = ISR_PREC_FP64;
+  b->engine = ENG_GENERAL;
+  b->dev_bytes = 256 + (size_t)nc * E * W * 8 + (size_t)nc * (E + 1) * 8 + (size_t)nc * E * n3 * 8;
+  b->dev = c->arena->alloc(b->dev_bytes, true);
+  const long long tiles = tiles_per_comp(f->order, E);
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t o_coef = 0, o_tau = al(o_coef + (size_t)nc * E * n3 * 8), o_st = al(o_tau + (size_t)nc * E * 8);
+  const size_t o_zero = al(o_st + (size_t)nc * sizeof(CompState));  // digits, error bins, look-back, ticket
+  const size_t o_hist = al(o_zero + elemcut_digit_bytes(nc));
+  const size_t o_lb = al(o_hist + (size_t)nc * HBINS * sizeof(HistBin));
+  const size_t o_tk = al(o_lb + (size_t)nc * tiles * 8);
+  const size_t scr_bytes = o_tk + 256;
+  char* scr = b->dev ? (char*)c->arena->alloc(scr_bytes) : nullptr;
+  if (!b->dev || !scr) {
+    if (b->dev) c->arena->free(b->dev);
+    delete b;
+    return fail(ISR_ENOMEM, "the per-element cut does not fit the HBM budget");
+  }
+  auto give_up = [&](int code) {
+    c->arena->free(scr);
+    isr_blob_free(b);
+    return code;
+  };
+  Job j;
+  std::memset(&j, 0, sizeof(j));
+  j.u = f->field;
+  j.jac = f->elem_jac;
+  j.comp_stride = f->comp_stride ? f->comp_stride : E * n3;
+  j.n_elem = E;
+  j.order = f->order;
+  j.ncomp = nc;
+  j.precision = ISR_PREC_FP64;
+  j.vbytes = 8;
+  j.tol = f->tol;
+  j.cut_scale = 1.0;
+  for (int k = 0; k < 8; ++k) j.Bov[k] = -1.0;
+  j.tab = c->tab[f->order];
+  j.st = (CompState*)(scr + o_st);
+  j.histR = (HistBin*)(scr + o_hist);
+  j.lookback = (u64*)(scr + o_lb);
+  j.ticket = (u32*)(scr + o_tk);
+  j.bitmap = b->bitmap();
+  j.elem_ptr = b->elem_ptr();
+  j.values = b->values();
+  j.voff = b->voff();
+  j.tau_elem = (const double*)(scr + o_tau);
+  double* coef = (double*)(scr + o_coef);
+  const int gfwd = (int)std::min<long long>(tiles * nc, (long long)c->num_cu * 8);
+  if (launch_pass(K_FORWARD, ISR_PREC_FP64, j, gfwd, s, coef) != hipSuccess)
+    return give_up(fail(ISR_EDEVICE, "forward transform failed: %s", hipGetErrorString(hipGetLastError())));
+  const int gsel = (int)std::max<long long>(1, std::min<long long>((E * nc + 3) / 4, (long long)c->num_cu * 8));
+  const int g3 = (int)std::min<long long>(tiles * nc, (long long)c->num_cu * resident_blocks(K_PASS3, ISR_PREC_FP64, f->order));
+  double scale[ISR_MAX_COMP];
+  for (int k = 0; k < ISR_MAX_COMP; ++k) scale[k] = 1.0;
+  CompState hs[ISR_MAX_COMP];
+  int iters = 0;
+  for (;;) {
+    std::memset(hs, 0, sizeof(hs));
+    for (int k = 0; k < nc; ++k) {
+      hs[k].tol = f->tol;
+      hs[k].n_values = (u64)(E * n3);
+      hs[k].bstar = -1;
+    }
+    if (hipMemcpyAsync(j.st, hs, nc * sizeof(CompState), hipMemcpyHostToDevice, s) != hipSuccess ||
+        launch_zero(scr + o_zero, o_tk + 256 - o_zero, s) != hipSuccess ||
+        launch_elemcut(j, coef, (double*)(scr + o_tau), (u64*)(scr + o_zero), scale, gsel, s) != hipSuccess ||
+        launch_pass(K_PASS3, ISR_PREC_FP64, j, g3, s) != hipSuccess || launch_finalize(j, s) != hipSuccess ||
+        hipMemcpyAsync(hs, j.st, nc * sizeof(CompState), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return give_up(fail(ISR_EDEVICE, "per-element cut failed: %s", hipGetErrorString(hipGetLastError())));
+    int flags = 0;
+    for (int k = 0; k < nc; ++k) flags |= hs[k].flags;
+    rc = status_from_flags(flags);
+    if (rc) return give_up(rc);
+    bool again = false;
+    if (iters < 4) {
+      for (int k = 0; k < nc; ++k) {
+        if (hs[k].rel > f->tol) {
+          const double fr = f->tol / hs[k].rel;
+          scale[k] = (scale[k] * (fr * fr)) * (1.0 - 0x1p-20);
+          again = true;
+        }
+      }
+    }
+    if (!again) break;
+    ++iters;
+  }
+  fill_stats(b, hs, st);
+  bool within = true;
+  for (int k = 0; k < nc; ++k) within = within && !(hs[k].rel > f->tol);
+  b->status = within ? ISR_OK : ISR_ETOL;
+  c->arena->free(scr);
+  if (st) {
+    st->repair_iters = iters;
+    st->status = b->status;
+    st->t_submit = t0;
+    st->t_done = now_s();
+  }
+  *out = b;
+  if (!within) fail(ISR_ETOL, "relative error above tol after %d budget repairs", iters);
+  return b->status;
+}
+
 }  // namespace isr
 
 extern "C" int isr_compress_quantized(isr_ctx* c, const isr_field* f, double share, isr_blob** out, isr_stats* st) {
@@ -1981,4 +2109,14 @@ extern "C" int isr_compress_quantized(isr_ctx* c, const isr_field* f, double sha
   if (rc) return rc;
   std::lock_guard<std::mutex> g(c->mu);
   return isr::run_compress_quantized(c, f, share, out, st);
+}
+
+extern "C" int isr_compress_elemcut(isr_ctx* c, const isr_field* f, isr_blob** out, isr_stats* st) {
+  if (!c || !out) return fail(ISR_EINVAL, "ctx or out is NULL");
+  *out = nullptr;
+  if (st) std::memset(st, 0, sizeof(*st));
+  int rc = set_device(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> g(c->mu);
+  return isr::run_compress_elemcut(c, f, out, st);
 }

@@ -91,6 +91,7 @@ def load_library(path: str = LIB_PATH):
         "isr_compress_batch": (I32, [P, C.POINTER(isr_field), I32, C.POINTER(P), C.POINTER(isr_stats)]),
         "isr_compress_noalloc": (I32, [P, C.POINTER(isr_field), P, U64, C.POINTER(U64), C.POINTER(isr_stats)]),
         "isr_compress_quantized": (I32, [P, C.POINTER(isr_field), C.c_double, C.POINTER(P), C.POINTER(isr_stats)]),
+        "isr_compress_elemcut": (I32, [P, C.POINTER(isr_field), C.POINTER(P), C.POINTER(isr_stats)]),
         "isr_submit": (I32, [P, C.POINTER(isr_field), C.POINTER(U64)]),
         "isr_poll": (I32, [P, U64, I32, C.POINTER(P), C.POINTER(isr_stats)]),
         "isr_decompress": (I32, [P, P, P, I32, P]),
@@ -375,6 +376,17 @@ class Context:
         rc = load_library().isr_compress_quantized(self._h, C.byref(f), float(share), C.byref(h), C.byref(st))
         if rc not in (OK, ETOL):
             _check(rc, "isr_compress_quantized")
+        return Blob(self, h.value, _stats_dict(st, f.ncomp), rc)
+
+    def compress_elemcut(self, u, order: int, tol: float, jac=None, stream=None) -> Blob:
+        """Per-element cut (FP64 path): every element cut alone at its own
+        share of the budget."""
+        f = self._field(u, order, tol, "fp64", jac, stream)
+        h = C.c_void_p()
+        st = isr_stats()
+        rc = load_library().isr_compress_elemcut(self._h, C.byref(f), C.byref(h), C.byref(st))
+        if rc not in (OK, ETOL):
+            _check(rc, "isr_compress_elemcut")
         return Blob(self, h.value, _stats_dict(st, f.ncomp), rc)
 
     def compress_noalloc(self, u, order: int, tol: float, out, precision="fp64", stream=None):
