@@ -365,6 +365,46 @@ def run_hybrid(u, order, prec, steps, host_threads=12, codecs=(("bzip2", 9, Fals
     return out
 
 
+def run_variants(ctx, u, order, steps, tols=(1e-2, 1e-3), codec=("zlib", 6, True)):
+    """Variants of the lossy step at equal tolerance on the FP64 path (the
+    plain global cut, the per-element cut, the quantised kept values with
+    half the budget left to the quantisation; BF16 for reference): ms per
+    snapshot, kept count, the compression ratio of the blob and of the blob
+    after the lossless coder, and the largest relative error."""
+    import torch
+
+    from paper_2407_20731_amd import isr
+
+    in_bytes = u.numel() * 8
+    kinds = {
+        "plain_fp64": lambda t: ctx.compress(u, order, t, "fp64"),
+        "plain_bf16": lambda t: ctx.compress(u, order, t, "bf16"),
+        "elemcut_fp64": lambda t: ctx.compress_elemcut(u, order, t),
+        "quantized_fp64": lambda t: ctx.compress_quantized(u, order, t, 0.5),
+    }
+    out = {"codec": f"{codec[0]}-{codec[1]}" + ("+shuffle" if codec[2] else ""), "steps": steps, "tols": []}
+    for tol in tols:
+        row = {"tol": tol}
+        for name, fn in kinds.items():
+            fn(tol).free()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                fn(tol).free()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / steps * 1e3
+            b = fn(tol)
+            raw = b.to_bytes()
+            packed = isr.pack_host(raw, *codec)
+            row[name] = {"ms": ms, "GBps_field": in_bytes / (ms / 1e3) / 1e9, "kept": sum(b.stats["kept"]),
+                         "cr_lossy": (in_bytes - len(raw)) / in_bytes,
+                         "cr_lossy_lossless": (in_bytes - len(packed)) / in_bytes,
+                         "max_rel_err": max(b.stats["rel_err"]), "status": b.status}
+            b.free()
+        out["tols"].append(row)
+    return out
+
+
 def serving_requests(pool, n_req, seed=5):
     """E lognormal (median 20k, sigma 1, clipped 1k-500k), N uniform in {5,7,9}."""
     import numpy as np
@@ -456,6 +496,8 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-hybrid", action="store_true", help="skip the hybrid lossless stage section")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the variants section (per-element cut, quantised values)")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--order", type=int, default=ORDER, help="order N of the single-snapshot section")
     ap.add_argument("--elements", type=int, default=E_BENCH, help="elements of the single-snapshot section")
@@ -596,6 +638,9 @@ def main() -> int:
     if not args.no_hybrid and head != "fp64":
         out["hybrid_lossless"] = run_hybrid(u, N, head, 5)
         log(f"hybrid lossless: {out['hybrid_lossless']}")
+    if not args.no_variants:
+        out["variants"] = run_variants(ctx_run, u, N, 5)
+        log(f"variants: {out['variants']}")
     gpu_res = {}
     if not args.no_cpu and (E, N) == (CPU_SAMPLE_ELEMS, ORDER):
         # one more (untimed) result per precision, kept on the host for the

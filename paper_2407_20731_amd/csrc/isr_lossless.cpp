@@ -25,6 +25,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <new>
 #include <thread>
 #include <vector>
 
@@ -67,7 +68,9 @@ BlobLayout blob_layout(const unsigned char* p, size_t n) {
   std::memcpy(&ne, p + 16, 8);
   std::memcpy(&vb, p + 24, 4);
   std::memcpy(&W, p + 28, 4);
-  if (ncomp < 1 || ncomp > ISR_MAX_COMP || ne < 1 || (vb != 4 && vb != 8) || W < 1) return L;
+  if (ncomp < 1 || ncomp > ISR_MAX_COMP || ne < 1 || (vb != 4 && vb != 8) || W < 1 || W > 64) return L;
+  // the bitmap and element offsets alone must fit in n bytes (no overflow below)
+  if ((uint64_t)ne > n / (8 * (uint64_t)ncomp * (uint64_t)(W + 1))) return L;
   const size_t off = 64 + 72 * (size_t)ncomp + (size_t)ncomp * ne * W * 8 + (size_t)ncomp * (ne + 1) * 8;
   if (off > n || (n - off) % vb) return L;
   L.values_off = off;
@@ -371,8 +374,8 @@ int packer_poll(Packer* p, uint64_t job, int wait_ms, void* out, uint64_t cap, u
 
 extern "C" {
 
-int isr_pack_host(const void* blob, uint64_t n, int32_t codec, int32_t level, uint32_t flags, int32_t threads,
-                  void* out, uint64_t cap, uint64_t* out_bytes) {
+static int pack_host(const void* blob, uint64_t n, int32_t codec, int32_t level, uint32_t flags, int32_t threads,
+                     void* out, uint64_t cap, uint64_t* out_bytes) {
   using namespace isr;
   if (!blob || !out_bytes) return set_error(ISR_EINVAL, "blob or out_bytes is NULL");
   int rc = check_codec(codec, level);
@@ -392,7 +395,7 @@ int isr_pack_host(const void* blob, uint64_t n, int32_t codec, int32_t level, ui
   return ISR_OK;
 }
 
-int isr_unpack_host(const void* packed, uint64_t n, void* out, uint64_t cap, uint64_t* out_bytes) {
+static int unpack_host(const void* packed, uint64_t n, void* out, uint64_t cap, uint64_t* out_bytes) {
   using namespace isr;
   if (!packed || !out_bytes) return set_error(ISR_EINVAL, "packed or out_bytes is NULL");
   const unsigned char* p = (const unsigned char*)packed;
@@ -418,7 +421,7 @@ int isr_unpack_host(const void* packed, uint64_t n, void* out, uint64_t cap, uin
     uint64_t cs;
     std::memcpy(&cs, p + PK_HDR + 8 * (size_t)k, 8);
     const uint64_t o = (uint64_t)k * csz, len = std::min<uint64_t>(csz, raw_n - o);
-    if (at + cs > n || !decode_chunk((int)codec, p + at, cs, raw.data() + o, len))
+    if (cs > n - at || !decode_chunk((int)codec, p + at, cs, raw.data() + o, len))
       return set_error(ISR_EINVAL, "corrupt ISRZ chunk %u", k);
     at += cs;
   }
@@ -431,6 +434,29 @@ int isr_unpack_host(const void* packed, uint64_t n, void* out, uint64_t cap, uin
     unshuffle(dst + L.values_off, raw.data() + L.values_off, L.values_bytes / L.vbytes, L.vbytes);
   }
   return ISR_OK;
+}
+
+// No C++ exception crosses the C ABI (allocation or thread creation failures
+// become error codes).
+int isr_pack_host(const void* blob, uint64_t n, int32_t codec, int32_t level, uint32_t flags, int32_t threads,
+                  void* out, uint64_t cap, uint64_t* out_bytes) {
+  try {
+    return pack_host(blob, n, codec, level, flags, threads, out, cap, out_bytes);
+  } catch (const std::bad_alloc&) {
+    return isr::set_error(ISR_ENOMEM, "host memory exhausted while packing");
+  } catch (...) {
+    return isr::set_error(ISR_EDEVICE, "packing failed on the host");
+  }
+}
+
+int isr_unpack_host(const void* packed, uint64_t n, void* out, uint64_t cap, uint64_t* out_bytes) {
+  try {
+    return unpack_host(packed, n, out, cap, out_bytes);
+  } catch (const std::bad_alloc&) {
+    return isr::set_error(ISR_ENOMEM, "host memory exhausted while unpacking");
+  } catch (...) {
+    return isr::set_error(ISR_EDEVICE, "unpacking failed on the host");
+  }
 }
 
 }  // extern "C"

@@ -67,137 +67,17 @@ static double now_s() {
 
 namespace isr {
 
-Arena::Arena(uint64_t budget) : budget_(budget) {}
-
-Arena::~Arena() { release(); }
-
-void Arena::release() {
-  for (auto& c : chunks_)
-    if (c.base) (void)hipFree(c.base);
-  chunks_.clear();
-  live_.clear();
-  held_ = 0;
-  used_ = 0;
-}
-
-void* Arena::alloc(size_t bytes, bool high) {
-  std::lock_guard<std::mutex> g(mu_);
-  bytes = (bytes + 255) & ~size_t(255);
-  if (bytes == 0) bytes = 256;
-  // low: first fitting range in address order; high: the last one
-  int best_c = -1;
-  size_t best_off = 0, best_sz = 0;
-  for (size_t ci = 0; ci < chunks_.size(); ++ci)
-    for (auto& fr : chunks_[ci].free)
-      if (fr.second >= bytes && (best_c < 0 || high)) {
-        best_c = (int)ci;
-        best_off = fr.first;
-        best_sz = fr.second;
-      }
-  if (best_c < 0) {
-    // a new chunk: 256 MB, or what is left of the budget, or at least `bytes`
-    auto wanted = [&] {
-      return std::max(bytes, std::min((size_t)(256ull << 20), (size_t)(budget_ > held_ ? budget_ - held_ : 0)));
-    };
-    size_t want = wanted();
-    if (held_ + want > budget_) {
-      // the budget is held in ranges too small for this request: give the
-      // chunks with nothing live in them back to the device and try again
-      for (auto& c : chunks_)
-        if (c.base && c.free.size() == 1 && c.free.begin()->first == 0 && c.free.begin()->second == c.size) {
-          (void)hipFree(c.base);
-          held_ -= c.size;
-          c.base = nullptr;
-          c.size = 0;
-          c.free.clear();
-        }
-      want = wanted();
-      if (held_ + want > budget_) return nullptr;
-    }
-    void* p = nullptr;
-    if (hipMalloc(&p, want) != hipSuccess) {
-      (void)hipGetLastError();
-      return nullptr;
-    }
-    Chunk c;
-    c.base = (char*)p;
-    c.size = want;
-    c.free[0] = want;
-    best_c = -1;
-    for (size_t ci = 0; ci < chunks_.size() && best_c < 0; ++ci)
-      if (!chunks_[ci].base) best_c = (int)ci;  // reuse a released slot (live_ keeps indices)
-    if (best_c < 0) {
-      chunks_.push_back(c);
-      best_c = (int)chunks_.size() - 1;
-    } else {
-      chunks_[best_c] = c;
-    }
-    held_ += want;
-    best_off = 0;
-    best_sz = want;
+// chunks of the arena come straight from the device allocator
+static void* dev_chunk_alloc(size_t bytes, void*) {
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
   }
-  Chunk& c = chunks_[best_c];
-  c.free.erase(best_off);
-  size_t at = best_off;
-  if (high) {
-    at = best_off + best_sz - bytes;
-    if (best_sz > bytes) c.free[best_off] = best_sz - bytes;
-  } else if (best_sz > bytes) {
-    c.free[best_off + bytes] = best_sz - bytes;
-  }
-  char* p = c.base + at;
-  live_[p] = {best_c, bytes};
-  used_ += bytes;
-  high_ = std::max(high_, used_);
   return p;
 }
 
-void Arena::give_back(int ci, size_t off, size_t sz) {
-  Chunk& c = chunks_[ci];
-  auto it = c.free.emplace(off, sz).first;
-  // merge with the next range
-  auto nx = std::next(it);
-  if (nx != c.free.end() && it->first + it->second == nx->first) {
-    it->second += nx->second;
-    c.free.erase(nx);
-  }
-  // merge with the previous range
-  if (it != c.free.begin()) {
-    auto pv = std::prev(it);
-    if (pv->first + pv->second == it->first) {
-      pv->second += it->second;
-      c.free.erase(it);
-    }
-  }
-}
-
-void Arena::free(void* p) {
-  if (!p) return;
-  std::lock_guard<std::mutex> g(mu_);
-  auto it = live_.find((char*)p);
-  if (it == live_.end()) return;
-  int ci = it->second.first;
-  size_t sz = it->second.second;
-  size_t off = (char*)p - chunks_[ci].base;
-  live_.erase(it);
-  used_ -= sz;
-  give_back(ci, off, sz);
-}
-
-void Arena::shrink(void* p, size_t bytes) {
-  std::lock_guard<std::mutex> g(mu_);
-  auto it = live_.find((char*)p);
-  if (it == live_.end()) return;
-  bytes = (bytes + 255) & ~size_t(255);
-  if (bytes == 0) bytes = 256;
-  size_t old = it->second.second;
-  if (bytes >= old) return;
-  int ci = it->second.first;
-  size_t off = (char*)p - chunks_[ci].base;
-  it->second.second = bytes;
-  used_ -= old - bytes;
-  give_back(ci, off + bytes, old - bytes);
-}
+static void dev_chunk_free(void* p, void*) { (void)hipFree(p); }
 
 }  // namespace isr
 
@@ -1331,7 +1211,8 @@ int isr_create(const isr_config* cfg, isr_ctx** out) {
   hipDeviceProp_t prop;
   HIPCHK(hipGetDeviceProperties(&prop, c->device));
   c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-  c->arena.reset(new isr::Arena(d.hbm_budget_bytes ? d.hbm_budget_bytes : (64ull << 30)));
+  c->arena.reset(new isr::Arena(d.hbm_budget_bytes ? d.hbm_budget_bytes : (64ull << 30), isr::dev_chunk_alloc,
+                                isr::dev_chunk_free, nullptr));
   for (auto& row : c->tile)
     for (auto& t : row) t = -1;
   if (d.autotune_path) {
@@ -1703,13 +1584,21 @@ int isr_pack_submit(isr_ctx* c, const isr_blob* b, int32_t codec, int32_t level,
   put_hdr(b, hdr);
   const size_t hb = isr_blob::HDR + isr_blob::CHDR * b->ncomp;
   const size_t body = b->bitmap_bytes() + b->ptr_bytes() + b->values_bytes();
-  return isr::packer_submit(c->packer, (const unsigned char*)hdr, hb, b->bitmap(), body, codec, level, flags, job);
+  try {
+    return isr::packer_submit(c->packer, (const unsigned char*)hdr, hb, b->bitmap(), body, codec, level, flags, job);
+  } catch (...) {  // no C++ exception crosses the C ABI
+    return fail(ISR_ENOMEM, "could not queue the blob for the lossless stage");
+  }
 }
 
 int isr_pack_poll(isr_ctx* c, uint64_t job, int32_t wait_ms, void* out, uint64_t cap, uint64_t* out_bytes,
                   double* seconds) {
   if (!c) return fail(ISR_EINVAL, "ctx is NULL");
-  return isr::packer_poll(c->packer, job, wait_ms, out, cap, out_bytes, seconds);
+  try {
+    return isr::packer_poll(c->packer, job, wait_ms, out, cap, out_bytes, seconds);
+  } catch (...) {
+    return fail(ISR_ENOMEM, "could not collect the packed blob");
+  }
 }
 
 void isr_blob_free(isr_blob* b) {

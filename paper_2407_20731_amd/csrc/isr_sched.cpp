@@ -114,41 +114,19 @@ int Scheduler::submit(const isr_field* f, uint64_t* req) {
 
 // Start queued requests (FIFO) while a stream slot and HBM budget are free.
 bool Scheduler::admit_locked() {
-  bool any = false;
-  while (!queue_.empty()) {
-    Slot* free_slot = nullptr;
-    for (auto& s : slots_)
-      if (!s.busy) {
-        free_slot = &s;
-        break;
-      }
-    if (!free_slot) break;
-    const uint64_t id = queue_.front();
+  auto start = [&](Slot& s, uint64_t id) {
     Req& r = reqs_[id];
-    (void)hipStreamWaitEvent(free_slot->s, r.ready, 0);
-    free_slot->t = Task();
-    const int rc = task_begin(ctx_, &r.f, free_slot->s, false, &free_slot->t);
-    if (rc == ISR_ENOMEM) {
-      bool running = false;
-      for (auto& s : slots_) running = running || s.busy;
-      if (running) break;  // wait until running requests free memory
-    }
-    queue_.pop_front();
-    if (rc != ISR_OK) {
-      r.done = true;
-      r.status = rc;
-      release_copy(r);
-      any = true;
-      continue;
-    }
-    free_slot->busy = true;
-    free_slot->id = id;
-    any = true;
-    uint64_t running = 0;
-    for (auto& s : slots_) running += s.busy;
-    if (running > high_) high_ = running;
-  }
-  return any;
+    (void)hipStreamWaitEvent(s.s, r.ready, 0);
+    s.t = Task();
+    return task_begin(ctx_, &r.f, s.s, false, &s.t);
+  };
+  auto end = [&](uint64_t id, int rc) {
+    Req& r = reqs_[id];
+    r.done = true;
+    r.status = rc;
+    release_copy(r);
+  };
+  return admit_fifo(queue_, slots_, ISR_ENOMEM, start, end, &high_);
 }
 
 void Scheduler::loop() {

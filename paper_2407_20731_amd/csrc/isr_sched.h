@@ -13,40 +13,10 @@
 #include <vector>
 
 #include "isr.h"
+#include "isr_arena.h"
 #include "isr_internal.h"
 
 namespace isr {
-
-// Device sub-allocator: large hipMalloc chunks, best-fit ranges, coalescing,
-// in-place shrink; never holds more than `budget` bytes of chunks.
-class Arena {
- public:
-  explicit Arena(uint64_t budget);
-  ~Arena();
-  // nullptr when the budget or the device is exhausted.  Short-lived scratch
-  // takes the lowest free range that fits; long-lived blobs (high = true) take
-  // the top of the highest one, so that shrunk blobs do not split the space
-  // scratch needs.
-  void* alloc(size_t bytes, bool high = false);
-  void free(void* p);
-  void shrink(void* p, size_t bytes);
-  void release();
-  uint64_t budget() const { return budget_; }
-  uint64_t used() const { return used_; }
-  uint64_t high_water() const { return high_; }
-
- private:
-  struct Chunk {
-    char* base;
-    size_t size;
-    std::map<size_t, size_t> free;  // offset -> length
-  };
-  void give_back(int ci, size_t off, size_t sz);
-  std::mutex mu_;
-  uint64_t budget_, held_ = 0, used_ = 0, high_ = 0;
-  std::vector<Chunk> chunks_;
-  std::map<char*, std::pair<int, size_t>> live_;
-};
 
 // Sizes and scratch layout of one compression.
 struct Sizes {
