@@ -6,18 +6,22 @@
 // One wavefront per element.  Its norm terms and energies are formed from
 // the field and the FP64 coefficients (isr_forward's), and the element's
 // threshold is found by a binary search over the bit patterns of the
-// energies (monotone for non-negative doubles).  Each probe decides
-// RN(exact sum of energies below the key) <= B_e: an FP64 wave sum with a
-// rigorous error bound settles almost every probe, and the rest are summed
-// exactly.  Exact sums go into 32-bit digits in LDS (X units of 2^-1075,
-// each FP64 term touching three digits), are carried into a wave big integer
-// and rounded once.  The workgroup adds every element's exact norm and
-// dropped energy into per-component digit totals, and the finishing kernel
-// rounds the component totals.  Compaction, the inverse and the exact error
-// check are pass 3 of the general pipeline, reading the per-element
+// energies (monotone for non-negative doubles), which stops once no energy
+// lies strictly inside the interval.  Each probe decides RN(exact sum of
+// energies below the key) <= B_e: an FP64 wave sum with a rigorous error
+// bound settles almost every probe, and the rest are summed exactly.  Exact
+// sums: every lane splits its terms by error-free extraction against 2^m >=
+// the wave's largest term into three FP64 sums (exact), their wave totals
+// form one 192-bit integer in a wave big integer (X units of 2^-1075), and
+// the rare remainders (bits far below 2^m) go through 32-bit digits in LDS;
+// the result is rounded once.  The workgroup adds every element's exact norm
+// and dropped energy into per-component digit totals, and the finishing
+// kernel rounds the component totals.  Compaction, the inverse and the exact
+// error check are pass 3 of the general pipeline, reading the per-element
 // thresholds.
 #include "isr.h"
 #include "isr_common.cuh"
+#include "isr_xsum.cuh"
 
 namespace isr {
 
@@ -94,6 +98,59 @@ DEV void tot_add(u64* T, u64 w) {
   atomicAdd((unsigned long long*)&T[2 * l + 1], (unsigned long long)(w >> 32));
 }
 
+DEV u64 wmax64(u64 v);
+
+// X-unit wave big integer of the exact sum of the terms x[k] with take[k]
+// (finite, >= 0) over the wave's lanes.
+template <int CNT>
+DEV u64 exact_words(const double (&x)[CNT], const bool (&take)[CNT], u64* D) {
+  u64 mk = 0ull;
+#pragma unroll
+  for (int k = 0; k < CNT; ++k) {
+    const u64 b = take[k] ? dbits(x[k]) : 0ull;
+    mk = b > mk ? b : mk;
+  }
+  mk = wmax64(mk);
+  if (mk == 0ull) return 0ull;
+  // every term is below 2^m (exponent of the largest term plus one)
+  int m = (int)(mk >> 52) - 1022;
+  m = m < XM_MIN ? XM_MIN : (m > XM_MAX ? XM_MAX : m);
+  constexpr int h = 7;  // a lane adds at most 64 = 2^(h-1) terms
+  const XParm P = xparm(m, h);
+  XAcc A = {0.0, 0.0, 0.0};
+  bool rem = false;
+#pragma unroll
+  for (int k = 0; k < CNT; ++k) {
+    double left;
+    rem = xadd_left(A, P, take[k] ? x[k] : 0.0, left) || rem;
+  }
+  long long K[3];
+  xints(A, P, K);
+  I192 z = {{0ull, 0ull, 0ull}};
+  const int sft[3] = {107 - 2 * h, 53 - h, 0};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    __int128 t = (__int128)K[i];
+    for (int mm = 32; mm > 0; mm >>= 1) t += shfl_xor128(t, mm);
+    i192_add_shl(z, t, sft[i]);
+  }
+  // z counts units u3 = 2^(m + 3h - 159), i.e. X units shifted by sh (>= 61)
+  const int sh = m + 3 * h - 159 + 1075;
+  u64 w = part_at(z.w[0], z.w[1], sh);
+  wb_add(w, part_at(z.w[2], 0ull, sh + 128));
+  if (ballot(rem)) {
+    ed_clear(D);
+#pragma unroll
+    for (int k = 0; k < CNT; ++k) {
+      XAcc scratch = {0.0, 0.0, 0.0};
+      double left = 0.0;
+      if (xadd_left(scratch, P, take[k] ? x[k] : 0.0, left) && left != 0.0) ed_add(D, left);
+    }
+    wb_add(w, ed_words(D));
+  }
+  return w;
+}
+
 DEV double wsum(double v) {
   for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
   return v;
@@ -123,24 +180,22 @@ DEV u64 wmax64(u64 v) {
 template <int CNT>
 DEV bool ec_feasible(const double (&x)[CNT], const u64 (&key)[CNT], u64 K, double B, double succB, u64* D) {
   double s = 0.0;
-  u64 c = 0;
+  int c = 0;
 #pragma unroll
   for (int k = 0; k < CNT; ++k) {
-    if (key[k] < K) {
-      s = s + x[k];
-      ++c;
-    }
+    const bool in = key[k] < K;
+    s = s + (in ? x[k] : 0.0);
+    c += __popcll(ballot(in));
   }
   const double S = wsum(s);
-  const double C = (double)wave_sum64(c);
+  const double C = (double)c;
   const double bound = ((2.0 * C) * 0x1p-53) * S;
   if (S + bound <= B) return true;
   if (S - bound > succB) return false;
-  ed_clear(D);
+  bool in[CNT];
 #pragma unroll
-  for (int k = 0; k < CNT; ++k)
-    if (key[k] < K) ed_add(D, x[k]);
-  return wb_round(ed_words(D)) <= B;
+  for (int k = 0; k < CNT; ++k) in[k] = key[k] < K;
+  return wb_round(exact_words<CNT>(x, in, D)) <= B;
 }
 
 }  // namespace
@@ -194,10 +249,10 @@ __global__ __launch_bounds__(256) void k_elemsel(Job j, const double* coef, doub
       continue;
     }
     // the element's norm, exactly, and its budget
-    ed_clear(D);
+    bool valid[CNT];
 #pragma unroll
-    for (int k = 0; k < CNT; ++k) ed_add(D, t[k]);
-    u64 w = ed_words(D);
+    for (int k = 0; k < CNT; ++k) valid[k] = lane + 64 * k < n3;
+    u64 w = exact_words<CNT>(t, valid, D);
     const double U2e = wb_round(w);
     tot_add(L.tot[comp][0], w);
     const double B = (tt * U2e) * sc.s[comp];
@@ -217,6 +272,13 @@ __global__ __launch_bounds__(256) void k_elemsel(Job j, const double* coef, doub
       }
       u64 lo = wmin64(mn), hi = wmax64(mx) + 1ull;  // S(lo) = 0 <= B; S(hi) = the total > B
       while (hi - lo > 1ull) {
+        // no energy strictly between lo and hi: then S(hi) = S(lo) plus the
+        // energies at key lo, and S(lo) <= B < S(hi) makes lo an energy's key
+        // (the answer); bisection stops here long before the keys run out
+        bool inside = false;
+#pragma unroll
+        for (int k = 0; k < CNT; ++k) inside = inside || (key[k] > lo && key[k] < hi);
+        if (!ballot(inside)) break;
         const u64 mid = lo + ((hi - lo) >> 1);
         if (ec_feasible<CNT>(x, key, mid, B, succB, D))
           lo = mid;
@@ -226,18 +288,14 @@ __global__ __launch_bounds__(256) void k_elemsel(Job j, const double* coef, doub
       kt = lo;  // S(lo) <= B < S(lo + 1): lo is the key of an energy
     }
     // dropped energy, exactly, and the kept count
-    ed_clear(D);
+    bool drop[CNT];
     u64 kc = 0;
 #pragma unroll
     for (int k = 0; k < CNT; ++k) {
-      if (lane + 64 * k < n3) {
-        if (key[k] < kt)
-          ed_add(D, x[k]);
-        else
-          ++kc;
-      }
+      drop[k] = valid[k] && key[k] < kt;
+      kc += (valid[k] && !drop[k]) ? 1ull : 0ull;
     }
-    w = ed_words(D);
+    w = exact_words<CNT>(x, drop, D);
     tot_add(L.tot[comp][1], w);
     kc = wave_sum64(kc);
     if (lane == 0) {
