@@ -198,7 +198,7 @@ static int check_field(const isr_field* f) {
 
 namespace isr {
 
-Sizes plan_sizes(const isr_field* f, int tile) {
+Sizes plan_sizes(const isr_field* f, int tile, bool full_lists) {
   Sizes z;
   const long long n = f->order + 1, n3 = n * n * n;
   const int nc = f->ncomp;
@@ -225,7 +225,7 @@ Sizes plan_sizes(const isr_field* f, int tile) {
   z.off_lookback = take((size_t)nc * z.tiles * 8);
   z.off_done = take(16 * 8 * sizeof(u32));
   z.zero_bytes = o;
-  z.list_cap = z.nv;
+  z.list_cap = full_lists || z.nv <= (1ull << 20) ? z.nv : std::max<u64>(z.nv / 8, 1ull << 20);
   z.off_lists = take((size_t)nc * 2 * z.list_cap * 8);  // list 0, then lists 1 and 2 at half size
   z.fast = fast_order(f->order, f->precision);
   z.tile = z.fast && f->precision != ISR_PREC_FP64 && dense_shape(f->order, tile) ? tile : 0;
@@ -511,7 +511,7 @@ int ctx_tile(const isr_ctx* c, int order, int precision) {
 
 // Footprint a request needs from the arena (scratch + worst-case blob).
 uint64_t request_footprint(const isr_field* f) {
-  Sizes z = plan_sizes(f, 0);
+  Sizes z = plan_sizes(f, 0, false);
   return (uint64_t)z.scratch_bytes + z.blob_max + 512;
 }
 
@@ -592,7 +592,7 @@ int task_begin(isr_ctx* c, const isr_field* f, hipStream_t s, bool timing, Task*
   t->f = *f;
   t->s = s;
   t->t_start = now_s();
-  t->z = plan_sizes(f, ctx_tile(c, f->order, f->precision));
+  t->z = plan_sizes(f, ctx_tile(c, f->order, f->precision), t->full_lists);
   t->scratch = (char*)c->arena->alloc(t->z.scratch_bytes);
   if (!t->scratch) return fail(ISR_ENOMEM, "scratch of %zu bytes does not fit the HBM budget", t->z.scratch_bytes);
   t->b = new_blob(c, f, t->z);
@@ -634,6 +634,33 @@ int task_step(Task* t, isr_blob** out) {
     }
     t->fast = false;
     t->j.sample_stride = 0;
+    int rc = task_enqueue(t);
+    if (rc) {
+      task_release(t);
+      return rc;
+    }
+    return ISR_PENDING;
+  }
+  if ((flags & ST_LIST) && !t->full_lists) {
+    // a candidate list outgrew its first-attempt capacity (energies bunched
+    // in a few exponent bins): the same attempt again with lists for every
+    // value, keeping the path and any budget override
+    double Bov[8];
+    std::memcpy(Bov, t->j.Bov, sizeof(Bov));
+    const long long ss = t->j.sample_stride;
+    t->full_lists = true;
+    t->c->arena->free(t->scratch);
+    t->z = plan_sizes(f, t->z.tile, true);
+    t->scratch = (char*)t->c->arena->alloc(t->z.scratch_bytes);
+    if (!t->scratch) {
+      task_release(t);
+      return fail(ISR_ENOMEM, "candidate lists for every value (%zu bytes of scratch) do not fit the HBM budget",
+                  t->z.scratch_bytes);
+    }
+    t->j = make_job(t->c, f, t->z, t->scratch, blob_ptrs(t->b));
+    t->j.cut_scale = t->cut_scale;
+    t->j.sample_stride = ss;
+    std::memcpy(t->j.Bov, Bov, sizeof(Bov));
     int rc = task_enqueue(t);
     if (rc) {
       task_release(t);

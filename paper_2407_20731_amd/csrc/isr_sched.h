@@ -36,7 +36,11 @@ struct Sizes {
   size_t scratch_bytes = 0;
   size_t blob_max = 0;       // worst-case blob allocation
 };
-Sizes plan_sizes(const isr_field* f, int tile);
+// full_lists: candidate lists for every value (no overflow possible); else a
+// first-attempt capacity of an eighth of the values (at least 2^20), which the
+// sampled window rarely exceeds; an overflow sets ST_LIST and the request is
+// rerun with full lists.
+Sizes plan_sizes(const isr_field* f, int tile, bool full_lists = true);
 int ctx_tile(const isr_ctx* c, int order, int precision);
 
 int enqueue_pipeline(isr_ctx* c, const Job& j, const Sizes& z, hipStream_t s, hipEvent_t* ev, bool fast);
@@ -80,6 +84,7 @@ struct Task {
   hipEvent_t ev[8] = {};
   bool timing = false;
   bool fast = false;         // this attempt runs the streaming path
+  bool full_lists = false;   // candidate lists sized for every value (after an overflow)
   int iters = 0;
   float repair_ms = 0.f;
   double t_start = 0;

@@ -161,3 +161,23 @@ def field_torch(n_elem: int, order: int, ncomp: int = 3, seed: int = 1, n_modes:
 def element_pool(n_elem: int, order: int, seed: int, ncomp: int = 3) -> np.ndarray:
     """A pool of elements from which request windows are taken."""
     return field(n_elem, order, ncomp=ncomp, seed=seed)
+
+
+def flat_spectrum(n_elem: int, order: int, ncomp: int = 1, seed: int = 1, spread: float = 1e-3) -> np.ndarray:
+    """Nodal fields whose Legendre coefficients all carry nearly the same
+    energy: c_pqr = s (1 + spread * U) / sqrt(gamma_p gamma_q gamma_r), random
+    signs s and U uniform in [0, 1), with the discrete GLL norms gamma_k =
+    2/(2k+1) and 2/N for k = N; u = sum c P_p(xi_i) P_q(xi_j) P_r(xi_k)
+    (numpy's Legendre evaluator at gll_points).  Every energy lies in
+    [1, (1 + spread)^2): one exponent bin holds (nearly) all of them, the
+    worst case for candidate lists built around a few bins."""
+    rng = np.random.default_rng(seed)
+    n = order + 1
+    x = gll_points(order)
+    P = np.polynomial.legendre.legvander(x, order)  # [node, degree]
+    gam = 2.0 / (2.0 * np.arange(n) + 1.0)
+    gam[-1] = 2.0 / order
+    g3 = gam[:, None, None] * gam[None, :, None] * gam[None, None, :]  # [r, q, p]
+    sign = rng.choice([-1.0, 1.0], size=(ncomp, n_elem, n, n, n))
+    c = sign * (1.0 + spread * rng.random((ncomp, n_elem, n, n, n))) / np.sqrt(g3)
+    return np.ascontiguousarray(np.einsum("kr,jq,ip,cerqp->cekji", P, P, P, c, optimize=True))

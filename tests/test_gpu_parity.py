@@ -213,3 +213,34 @@ def test_submit_poll_matches_compress(isr_ctx):
     blobs = [isr_ctx.poll(r, wait_ms=-1) for r in reqs]
     for t, b in zip((1e-2, 1e-3), blobs):
         assert b.to_bytes() == isr_ctx.compress(u, 7, t).to_bytes()
+
+
+def test_candidate_list_overflow_reruns_with_full_lists(isr_ctx):
+    """A field whose 1,179,648 energies per component all lie in one exponent
+    bin (synth.flat_spectrum): the sampled window holds every value, more than
+    a request's first-attempt candidate capacity (an eighth of the values, at
+    least 2^20), so the first attempt overflows and the request is rerun with
+    lists for every value.  The FP64 result equals the oracle's bit for bit;
+    BF16 meets the bound with the exact norm."""
+    from oracle.compress import energies, norm_terms
+    from oracle.exact import exact_sum
+    from oracle.tables import gll_tables
+    E, N = 2304, 7
+    print(f"[case] flat spectrum E={E} N={N}", flush=True)
+    u_np = synth.flat_spectrum(E, N, ncomp=1, seed=5)
+    T = gll_tables(N)
+    en = energies(oracle.forward(u_np[0], T.A), T.g3, None)
+    nv = E * (N + 1) ** 3
+    assert nv > (1 << 20) and np.unique(np.frexp(en)[1]).size == 1  # every value in the window
+    u = torch.from_numpy(u_np).cuda()
+    ref = oracle.compress(u_np, N, 1e-3, keep_arrays=True).comps[0]
+    blob = isr_ctx.compress(u, N, 1e-3, "fp64")
+    arr = blob.arrays()
+    h = arr.comps[0]
+    assert blob.status == 0
+    assert h["U2"] == ref.U2 and h["tau"] == ref.tau and h["kept"] == ref.kept and h["rel_err"] == ref.rel_err
+    assert np.array_equal(arr.bitmap[0], ref.bitmap)
+    assert np.array_equal(arr.values[0].view(np.uint64), ref.values.view(np.uint64))
+    b16 = isr_ctx.compress(u, N, 1e-3, "bf16")
+    assert b16.status == 0 and b16.stats["rel_err"][0] <= 1e-3
+    assert b16.arrays().comps[0]["U2"] == exact_sum(norm_terms(u_np[0], T.w3, None))

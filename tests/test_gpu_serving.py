@@ -74,9 +74,11 @@ def test_budget_bounds_admission():
     from paper_2407_20731_amd import isr
     pools = _pools((7,), 4000, seed0=600)
     u = pools[7]
-    # the whole pool (4000 elements) needs ~125 MB of scratch + blob, a window
-    # of 1500 elements ~47 MB: at most two windows fit at once
-    with isr.Context(device=0, max_inflight=8, budget_bytes=100 << 20) as ctx:
+    # the whole pool (4000 elements, 2.0 M values per component: candidate
+    # lists of 2^20 on the first attempt) needs ~89 MB of scratch + blob, a
+    # window of 1500 elements (lists for every value) ~57 MB: one window at a
+    # time fits the 80 MB budget
+    with isr.Context(device=0, max_inflight=8, budget_bytes=80 << 20) as ctx:
         # one request alone above the budget is refused at submit
         with pytest.raises(isr.IsrError) as e:
             ctx.submit(u, 7, 1e-3, "fp32")
