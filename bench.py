@@ -340,6 +340,14 @@ def run_hybrid(u, order, prec, steps, host_threads=12, codecs=(("bzip2", 9, Fals
         alone = (time.perf_counter() - t0) / steps * 1e3
         out["gpu_ms_alone"] = alone
         for codec, level, shuffle in codecs:
+            # one untimed round in the timed pattern (each blob's copy to the
+            # host overlapping the next compression, the codec's first use):
+            # its one-time costs stay out of the measurement
+            for b, jid in [(b, ctx.pack_submit(b, codec, level, shuffle))
+                           for b in (ctx.compress(u, order, TOL, prec) for _ in range(steps))]:
+                ctx.pack_poll(jid, wait_ms=-1)
+                b.free()
+            torch.cuda.synchronize()
             pend = []
             t0 = time.perf_counter()
             for _ in range(steps):

@@ -257,7 +257,18 @@ struct Packer {
       Job* j = jobs[queue.front()].get();
       queue.pop_front();
       g.unlock();
-      int rc = hipEventSynchronize(j->copied) == hipSuccess ? ISR_OK : ISR_EDEVICE;
+      // wait for the blob's copy by polling: a blocking wait here would sit
+      // inside the runtime beside the submitting thread's launches
+      int rc = ISR_OK;
+      for (;;) {
+        const hipError_t q = hipEventQuery(j->copied);
+        if (q == hipSuccess) break;
+        if (q != hipErrorNotReady) {
+          rc = ISR_EDEVICE;
+          break;
+        }
+        std::this_thread::sleep_for(std::chrono::microseconds(100));
+      }
       std::vector<unsigned char> raw, out;
       if (rc == ISR_OK) {
         // the serialized blob: header (taken at submit) and the copied body
@@ -299,7 +310,8 @@ Packer* packer_create(int device, int threads) {
   std::unique_ptr<Packer> p(new Packer());
   p->device = device;
   p->threads = threads > 0 ? threads : host_threads_default();
-  if (hipStreamCreateWithFlags(&p->s, hipStreamNonBlocking) != hipSuccess) return nullptr;  // default priority
+  // the copy stream is created at the first submit: a context that never
+  // packs holds none (the device has few hardware queues to share)
   Packer* raw = p.get();
   p->worker = std::thread([raw] { raw->loop(); });
   return p.release();
@@ -319,6 +331,11 @@ int packer_submit(Packer* p, const unsigned char* hdr, size_t hb, const void* de
   j->ser.assign(hdr, hdr + hb);  // the header only: the body is assembled by the packer's thread
   {
     std::lock_guard<std::mutex> g(p->mu);
+    if (!p->s && hipStreamCreateWithFlags(&p->s, hipStreamNonBlocking) != hipSuccess) {  // default priority
+      p->s = nullptr;
+      (void)hipGetLastError();
+      return set_error(ISR_EDEVICE, "could not create the lossless stage's copy stream");
+    }
     j->pinned = p->take(body, &j->staged);
   }
   if (!j->pinned) return set_error(ISR_ENOMEM, "pinned staging of %zu bytes failed", body);

@@ -24,9 +24,10 @@ int run_batch_sequential(isr_ctx* c, const isr_field* fs, int count, isr_blob** 
 
 Scheduler::Scheduler(isr_ctx* c) : ctx_(c) {
   const int n = ctx_max_inflight(c);
+  // each slot's stream is created when the slot first takes a request: a
+  // context that never serves holds no streams (the device has few hardware
+  // queues, and streams created beyond them share queues with other work)
   slots_.resize(n);
-  (void)hipSetDevice(ctx_device(c));
-  for (auto& s : slots_) (void)hipStreamCreateWithFlags(&s.s, hipStreamNonBlocking);  // default priority
   worker_ = std::thread([this] { loop(); });
 }
 
@@ -43,7 +44,7 @@ Scheduler::~Scheduler() {
       (void)hipStreamSynchronize(s.s);
       task_release(&s.t);
     }
-    (void)hipStreamDestroy(s.s);
+    if (s.s) (void)hipStreamDestroy(s.s);
   }
   for (auto& kv : reqs_) {
     if (kv.second.blob) isr_blob_free(kv.second.blob);
@@ -115,6 +116,11 @@ int Scheduler::submit(const isr_field* f, uint64_t* req) {
 // Start queued requests (FIFO) while a stream slot and HBM budget are free.
 bool Scheduler::admit_locked() {
   auto start = [&](Slot& s, uint64_t id) {
+    if (!s.s && hipStreamCreateWithFlags(&s.s, hipStreamNonBlocking) != hipSuccess) {  // default priority
+      s.s = nullptr;
+      (void)hipGetLastError();
+      return (int)set_error(ISR_EDEVICE, "could not create a stream for a request slot");
+    }
     Req& r = reqs_[id];
     (void)hipStreamWaitEvent(s.s, r.ready, 0);
     s.t = Task();
