@@ -230,7 +230,9 @@ DEV void sampleD_body(const Job& j, int comp, int vb, int nvb, SampleLdsD<N, PRE
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int v = 64 * s + lane;
-      ut[s] = v < nv ? __builtin_nontemporal_load(tile + v) : 0.0;
+      // every lane loads (from inside the tile), then masks: no branch per slot
+      const double lv = __builtin_nontemporal_load(tile + (v < nv ? v : nv - 1));
+      ut[s] = v < nv ? lv : 0.0;
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -342,7 +344,9 @@ DEV void passAD_body(const Job& j, int comp, int vb, int nvb, PassALdsD<N, PREC,
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int v = 64 * s + lane;
-      ut[s] = v < nv ? __builtin_nontemporal_load(tile + v) : 0.0;
+      // every lane loads (from inside the tile), then masks: no branch per slot
+      const double lv = __builtin_nontemporal_load(tile + (v < nv ? v : nv - 1));
+      ut[s] = v < nv ? lv : 0.0;
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -480,7 +484,9 @@ DEV void passBD_body(const Job& j, int comp, int vb, int nvb, PassBLdsD<N, PREC,
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int v = 64 * s + lane;
-      ur[s] = v < nv ? __builtin_nontemporal_load(tile + v) : 0.0;
+      // every lane loads (from inside the tile), then masks: no branch per slot
+      const double lv = __builtin_nontemporal_load(tile + (v < nv ? v : nv - 1));
+      ur[s] = v < nv ? lv : 0.0;
       buf[v] = (float)ur[s];
     }
     G::forward(buf, mt, lane);

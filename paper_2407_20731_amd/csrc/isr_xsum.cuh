@@ -62,8 +62,15 @@ DEV void slow_bin(HistBin* g, double v) {
 // Branch-free form: adds x to the three sums and returns what is left for
 // the exact global bins (0 for almost every term; x itself when x is not in
 // [0, M], which includes Inf and NaN).
+// 0 <= x < M = 2^m by the high words alone (M's low word is zero): a set
+// sign bit, Inf and NaN fail, and so does x == M, which then takes the exact
+// slow path like any term out of range.
+DEV bool xin(const XParm& P, double x) {
+  return (u32)((u64)__double_as_longlong(x) >> 32) < (u32)((u64)__double_as_longlong(P.M) >> 32);
+}
+
 DEV double xadd_r(XAcc& A, const XParm& P, double x) {
-  const bool in = x >= 0.0 && x <= P.M;
+  const bool in = xin(P, x);
   const double y = in ? x : 0.0;
   const double q1 = (P.S1 + y) - P.S1;
   const double r1 = y - q1;
@@ -81,7 +88,7 @@ DEV double xadd_r(XAcc& A, const XParm& P, double x) {
 // left for the exact global bins, and then `left` is what (the selection
 // that forms it is only needed on that rarely taken branch).
 DEV bool xadd_left(XAcc& A, const XParm& P, double x, double& left) {
-  const bool in = x >= 0.0 && x <= P.M;
+  const bool in = xin(P, x);
   const double y = in ? x : 0.0;
   const double q1 = (P.S1 + y) - P.S1;
   const double r1 = y - q1;
