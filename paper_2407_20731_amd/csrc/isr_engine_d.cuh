@@ -172,6 +172,15 @@ constexpr int dense_minb_b() {
   return N + 1 <= 7 ? 4 : ISR_DENSE_MINB;
 }
 
+// pass A launch bound of shape (N, T): four workgroups per CU (128 VGPRs,
+// a 44-byte spill) at N = 5 with tiles of up to two elements, measured 10 %
+// faster there than three; other shapes spill hundreds of bytes at 128, and
+// two workgroups at N = 9 measured 12 % slower than three
+template <int N, int T>
+constexpr int dense_minb_a() {
+  return (N == 5 && T <= 2) ? 4 : ISR_DENSE_MINB;
+}
+
 // Element (within the tile) and flat index of dense position v (positions
 // past the tile, which are masked out, keep f inside the tables).
 template <class G>
@@ -431,7 +440,7 @@ DEV void passAD_body(const Job& j, int comp, int vb, int nvb, PassALdsD<N, PREC,
 }
 
 template <int N, int PREC, int T>
-__global__ __launch_bounds__(256, ISR_DENSE_MINB) void k_passAD(Job j) {
+__global__ __launch_bounds__(256, (dense_minb_a<N, T>())) void k_passAD(Job j) {
   __shared__ PassALdsD<N, PREC, T> L;
   passAD_body<N, PREC, T>(j, blockIdx.y, blockIdx.x, gridDim.x, L);
 }
