@@ -221,8 +221,9 @@ DEV void refine_body(const Job& j, int comp, int L, u64 (*h)[2], u64 item, u64 n
   const u64 stride = nitems * 256;
   // the loop trip count is the same for every lane of a wave (ballots inside)
   const u64 nin_r = (nin + 63) & ~63ull;
-  // four entries per lane per step, loaded before any is used
-  constexpr int U = 4;
+  // sixteen entries per lane per step, loaded before any is used (the lists
+  // run to millions of entries: more loads in flight per lane)
+  constexpr int U = 16;
   for (u64 i0 = item * 256 + tid; i0 < nin_r; i0 += U * stride) {
     u64 keys[U];
 #pragma unroll
