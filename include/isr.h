@@ -60,7 +60,7 @@ extern "C" {
 #define ISR_ENOMEM (-2)     /* footprint above the HBM budget, or allocation failed */
 #define ISR_EDEVICE (-3)    /* a HIP call failed */
 #define ISR_ETOL (-4)       /* error bound not met after the rounding repair */
-#define ISR_ECANCELED (-5)
+/* (-5 is not used) */
 #define ISR_ENOTFOUND (-6)  /* unknown request id */
 
 /* ---- precisions of the transforms ------------------------------------- */
@@ -169,17 +169,21 @@ typedef struct {
 
 /* Create a context on cfg->device (cfg may be NULL: device 0, defaults).
  * Computes the GLL/Legendre tables on the host for every order and uploads
- * them.  Errors: ISR_EINVAL, ISR_EDEVICE. */
+ * them (the element basis of the lossy step, Sec. IV-B).  Errors:
+ * ISR_EINVAL, ISR_EDEVICE. */
 int isr_create(const isr_config *cfg, isr_ctx **out);
 
 /* Destroy a context: waits for its requests, frees its device memory.  Blobs
- * of this context must be freed first. */
+ * of this context must be freed first.  (Runtime only: no passage of the
+ * paper defines it.) */
 int isr_destroy(isr_ctx *ctx);
 
 /* Text of the last error on the calling thread (valid until its next call). */
 const char *isr_last_error(void);
 
-/* Compress one snapshot and wait for the result.  On ISR_OK or ISR_ETOL,
+/* Compress one snapshot and wait for the result: steps 1-5 above, the lossy
+ * step of Sec. IV-B run synchronously on the application's GPU (the
+ * synchronous approach of Sec. III-A).  On ISR_OK or ISR_ETOL,
  * *out receives a device-resident blob owned by the caller (isr_blob_free);
  * with ISR_ETOL the blob's measured error exceeds tol.  st may be NULL.
  * Errors: ISR_EINVAL (null/misaligned pointer, order, n_elem, ncomp, NaN
@@ -187,6 +191,7 @@ const char *isr_last_error(void);
 int isr_compress(isr_ctx *ctx, const isr_field *f, isr_blob **out, isr_stats *st);
 
 /* ---- allocation-free compression ----------------------------------------
+ * (Runtime only: no passage of the paper defines it.)
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
  * compression as isr_compress (same kernels, same result, byte for byte),
@@ -249,7 +254,8 @@ int isr_compress_quantized(isr_ctx *ctx, const isr_field *f, double share, isr_b
 int isr_compress_elemcut(isr_ctx *ctx, const isr_field *f, isr_blob **out, isr_stats *st);
 
 /* Compress several snapshots (orders may differ) in one batched launch
- * sequence.  FP64 snapshots of orders 5, 7 and 9: one persistent launch of
+ * sequence (the lossy step of Sec. IV-B over the snapshots a run writes
+ * periodically, several of them at once).  FP64 snapshots of orders 5, 7 and 9: one persistent launch of
  * the general passes.  FP32 / BF16: one streaming pipeline per snapshot on
  * the scheduler's streams, largest first; with ISR_FLAG_BATCH_PERSISTENT and
  * at least 8 snapshots of orders 5, 7 and 9, one persistent launch of the
@@ -262,7 +268,9 @@ int isr_compress_elemcut(isr_ctx *ctx, const isr_field *f, isr_blob **out, isr_s
 int isr_compress_batch(isr_ctx *ctx, const isr_field *fs, int32_t count, isr_blob **outs,
                        isr_stats *st);
 
-/* Queue a snapshot for compression and return at once with a request id.
+/* Queue a snapshot for compression and return at once with a request id
+ * (the application continues while the lossy step runs: the asynchronous
+ * side of Sec. III-A's hybrid approach).
  * Requests are admitted to the device while their footprint fits the HBM
  * budget and fewer than max_inflight are resident; later arrivals join the
  * running ones (continuous batching).  The field must stay unchanged until
@@ -278,7 +286,9 @@ int isr_submit(isr_ctx *ctx, const isr_field *f, uint64_t *req);
  * until done.  ISR_ENOTFOUND for an unknown or retired id. */
 int isr_poll(isr_ctx *ctx, uint64_t req, int32_t wait_ms, isr_blob **out, isr_stats *st);
 
-/* Reconstruct the nodal field from a blob into d_out (DEVICE, same layout as
+/* Reconstruct the nodal field from a blob (Sec. IV-B: the kept coefficients
+ * transformed back; the error bound is stated on this field) into d_out
+ * (DEVICE, same layout as
  * the input with comp_stride = n_elem * n^3), FP64 (out_prec ISR_PREC_FP64)
  * or FP32 (ISR_PREC_FP32).  The inverse is the one whose result the
  * compression measured, so the blob's rel_err is the error of this output:
@@ -288,15 +298,17 @@ int isr_poll(isr_ctx *ctx, uint64_t req, int32_t wait_ms, isr_blob **out, isr_st
  * the call returns after enqueueing.  Errors: ISR_EINVAL, ISR_EDEVICE. */
 int isr_decompress(isr_ctx *ctx, const isr_blob *b, void *d_out, int32_t out_prec, void *stream);
 
-/* Forward transform only (no truncation): coefficients c[comp][e][r][q][p]
- * (p fastest) into d_coef (DEVICE, FP64 for ISR_PREC_FP64, else FP32), in
+/* Forward transform only (step 1 above, Sec. IV-B; no truncation):
+ * coefficients c[comp][e][r][q][p] (p fastest) into d_coef (DEVICE, FP64 for ISR_PREC_FP64, else FP32), in
  * the requested precision.  FP64 order: t1 = sum_i A[p][i] u[k][j][i], then
  * t2 = sum_j A[q][j] t1[k][j][p], then c = sum_k A[r][k] t2[k][q][p], each
  * sum started from its first product and accumulated in ascending index with
  * separately rounded multiply and add.  Synchronous. */
 int isr_forward(isr_ctx *ctx, const isr_field *f, void *d_coef);
 
-/* Blob queries and (de)serialisation.  Serialized layout (little endian):
+/* Blob queries and (de)serialisation of the compressed snapshot (Sec. IV-B:
+ * the kept coefficients and where they sit; its size gives the compression
+ * ratio of Sec. IV-C).  Serialized layout (little endian):
  *   "ISR1", u32 version=3, i32 order, i32 ncomp, i64 n_elem, i32 value_bytes
  *   (8 or 4), i32 words_per_elem W = ceil(n^3/64), f64 tol, i32 precision,
  *   i32 status, i32 engine (FP32 / BF16: 0 general passes, 1 wave-tile or
@@ -357,7 +369,7 @@ int isr_pack_poll(isr_ctx *ctx, uint64_t job, int32_t wait_ms, void *out, uint64
                   double *seconds);
 
 /* ---- tile shapes and the autotuner --------------------------------------
- * The FP32 / BF16 streaming passes come in several tile shapes per order.
+ * (Runtime only: no passage of the paper defines them.)  The FP32 / BF16 streaming passes come in several tile shapes per order.
  * Shape 0 is the wave-tile engine: a wavefront owns 64 / (N+1)^2 elements
  * (one from N = 7 up) and works in the MFMA register layout.  Shape T > 0 is
  * the dense-tile engine: a wavefront owns T consecutive elements and does all
@@ -395,8 +407,9 @@ int isr_set_tile(isr_ctx *ctx, int32_t order, int32_t precision, int32_t tile);
  * NULL.  Errors: as isr_compress; ISR_EINVAL for FP64 (it has one shape). */
 int isr_autotune(isr_ctx *ctx, const isr_field *f, int32_t reps, isr_tune_report *rep);
 
-/* Host-only: the library's own FP64 tables for order N (each entry the
- * correctly rounded value of the exact quantity): xi[n], w[n], V[n*n]
+/* Host-only: the library's own FP64 tables for order N, the GLL basis of the
+ * lossy step (Sec. IV-B); each entry is the correctly rounded value of the
+ * exact quantity: xi[n], w[n], V[n*n]
  * (V[i*n+k] = P_k(xi_i)), A[n*n] (A[p*n+i] = (V^-1)[p][i]), gamma[n],
  * w3[n^3] (w3[(k*n+j)*n+i] = w_k w_j w_i), g3[n^3] (gamma_r gamma_q gamma_p).
  * Any pointer may be NULL.  No GPU needed.  Errors: ISR_EINVAL. */

@@ -167,8 +167,8 @@ DEV void gather_body(const Job& j, int comp, int vb, int nvb, GatherLds& X, bool
   const u64* list = list_ptr(j, comp, 0);
   const u64 nl = st->list_count[0] < j.list_cap ? st->list_count[0] : j.list_cap;
   u64 acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // (cnt, lo, hi) of the three window bins
-  // four entries per lane per step, loaded before any is used
-  constexpr int U = 4;
+  // sixteen entries per lane per step, loaded before any is used
+  constexpr int U = 16;
   const u64 stride = (u64)nvb * 256;
   for (u64 i0 = (u64)vb * 256 + tid; i0 < nl; i0 += U * stride) {
     u64 keys[U];

@@ -347,7 +347,11 @@ static FastGrids fast_setup(isr_ctx* c, Job& j, const Sizes& z) {
   FastGrids g;
   const long long ss = j.sample_stride > 0 ? j.sample_stride : 1;
   const long long stiles = (ftiles + ss - 1) / ss;
-  g.gs = (int)std::max<long long>(1, std::min<long long>(64, (stiles + 15) / 16));
+  // sixteen sampled tiles per workgroup; one per wavefront at N >= 8, whose
+  // tiles are large (1000+ values): there the serial chain of tiles per
+  // wavefront costs more than the extra workgroups' histogram atomics
+  g.gs = (int)std::max<long long>(1, j.order >= 8 ? std::min<long long>(256, (stiles + 3) / 4)
+                                                  : std::min<long long>(64, (stiles + 15) / 16));
   // list passes over ~2 % of the values; few refinement workgroups (each
   // flushes up to RBINS sub-bins with global atomics: 32 per component beat
   // 16 and 64 at 100M values)

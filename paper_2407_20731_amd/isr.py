@@ -26,7 +26,7 @@ import torch  # noqa: F401  (must precede loading libisr.so)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libisr.so")
 
-OK, PENDING, EINVAL, ENOMEM, EDEVICE, ETOL, ECANCELED, ENOTFOUND = 0, 1, -1, -2, -3, -4, -5, -6
+OK, PENDING, EINVAL, ENOMEM, EDEVICE, ETOL, ENOTFOUND = 0, 1, -1, -2, -3, -4, -6
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 FLAG_TIMING = 1
 FLAG_BATCH_PERSISTENT = 4  # FP32/BF16 batches (>= 8, orders 5/7/9) as one persistent launch
@@ -36,7 +36,7 @@ NPHASE = 9
 PHASES = ("pass1", "select1", "pass2", "refine", "pass3", "finalize", "repair", "fallback", "sample")
 PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16": PREC_BF16}
 _STATUS = {OK: "ISR_OK", PENDING: "ISR_PENDING", EINVAL: "ISR_EINVAL", ENOMEM: "ISR_ENOMEM",
-           EDEVICE: "ISR_EDEVICE", ETOL: "ISR_ETOL", ECANCELED: "ISR_ECANCELED", ENOTFOUND: "ISR_ENOTFOUND"}
+           EDEVICE: "ISR_EDEVICE", ETOL: "ISR_ETOL", ENOTFOUND: "ISR_ENOTFOUND"}
 
 
 class IsrError(RuntimeError):
