@@ -233,7 +233,7 @@ def against_oracle(gpu: dict, ref, u) -> dict:
             d = rec[c] - rc.recon
             row = {"kept": int(h["kept"]), "kept_oracle": int(rc.kept), "tau_rel_diff": float(h["tau"] / rc.tau - 1.0),
                    "rel_err": float(h["rel_err"]), "rel_err_oracle": float(rc.rel_err),
-                   "U2_equal": bool(h["U2"] == rc.U2),
+                   "U2_rel_diff": float(h["U2"] / rc.U2 - 1.0) if rc.U2 > 0 else 0.0,
                    "recon_rel_l2_vs_oracle": float(np.sqrt(np.sum(d * d) / np.sum(u[c] * u[c])))}
             if p == "fp64":
                 row["bit_exact"] = bool(h["tau"] == rc.tau and np.array_equal(arr.bitmap[c], rc.bitmap) and

@@ -23,15 +23,18 @@
  *      it lowers B by (tol/rel)^2 * (1 - 2^-20) and repeats 3-5 (at most 4
  *      times; then ISR_ETOL).
  *
- * U2 is the correctly rounded value of the exact sum of its FP64 terms on
- * every path.  With ISR_PREC_FP64 so are S and err2, and the transforms use
- * one fixed evaluation order (see isr_forward), so every coefficient, energy
- * and threshold is reproducible bit for bit by a CPU implementation of the
- * same definition.  With ISR_PREC_FP32 / ISR_PREC_BF16, whose energies and
- * reconstruction carry the transform error, each lane adds its energy and
- * error terms in a fixed FP64 order and only the lane totals are combined
- * exactly: S and err2 are deterministic (the same alone, in a batch or in
- * the serving mix) but not correctly rounded (relative error below 1e-12).
+ * With ISR_PREC_FP64, U2, S and err2 are the correctly rounded values of the
+ * exact sums of their FP64 terms, and the transforms use one fixed
+ * evaluation order (see isr_forward), so every coefficient, energy and
+ * threshold is reproducible bit for bit by a CPU implementation of the same
+ * definition.  With ISR_PREC_FP32 / ISR_PREC_BF16, whose energies and
+ * reconstruction carry the transform error anyway, each lane adds its norm,
+ * energy and error terms in a fixed FP64 order and only the lane totals are
+ * combined exactly: U2, S and err2 are deterministic (the same alone, in a
+ * batch or in the serving mix) but not correctly rounded: the relative error
+ * is at most (terms per lane) 2^-53, which stays below 1e-12 up to about 10^6
+ * elements at N = 7 (the typical error is far smaller).
+ * On these paths U2 still comes from the FP64 field and FP64 products.
  *
  * Conventions
  *   - Every function returns an int status (ISR_OK or a negative ISR_E*),

@@ -477,6 +477,7 @@ DEV void passA_body(const Job& j, int comp, int vb, int nvb, PassALds<N, PREC>& 
   __syncthreads();
   XAcc an = {0.0, 0.0, 0.0}, ae = {0.0, 0.0, 0.0};
   double pe = 0.0;  // fixed-order sum of the energies below the window
+  double pn = 0.0;  // MFMA paths: fixed-order sum of the norm terms
   u64 hi_tot = 0ull;
   u32 ncap = 0u;
   const double* ub = j.u + (size_t)comp * j.comp_stride;
@@ -509,14 +510,21 @@ DEV void passA_body(const Job& j, int comp, int vb, int nvb, PassALds<N, PREC>& 
 #pragma unroll
       for (int s = 0; s < NS; ++s) wq[s] = L.tab.w3[s][lane];
     }
+    // norm terms: every term split exactly on the FP64 path; on the MFMA
+    // paths each lane sums its terms in a fixed FP64 order and only the lane
+    // totals are added exactly (as for the energies and the error terms)
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const double x = G::valid(s, lane, ne) ? wq[s] * (u[s] * u[s]) : 0.0;
-      double r;
-      if (xadd_left(an, PN, x, r)) slow_bin(gN, r);
-      // one slot at a time: interleaving them would hold every slot's
-      // temporaries at once and cut the occupancy
-      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (EXACT) {
+        double r;
+        if (xadd_left(an, PN, x, r)) slow_bin(gN, r);
+        // one slot at a time: interleaving them would hold every slot's
+        // temporaries at once and cut the occupancy
+        __builtin_amdgcn_sched_barrier(0);
+      } else {
+        pn += x;
+      }
     }
     G::forward(u, c, L.buf[wv], mt, j.tab, lane);
     if (EPW > 1) {
@@ -582,6 +590,8 @@ DEV void passA_body(const Job& j, int comp, int vb, int nvb, PassALds<N, PREC>& 
   if constexpr (!EXACT) {
     const double r = xadd_sum(ae, PE, pe);
     if (r != 0.0) slow_bin(gE, r);
+    const double rn = xadd_sum(an, PN, pn);
+    if (rn != 0.0) slow_bin(gN, rn);
   }
   long long v[7];
   long long kn[3], ke[3];

@@ -338,6 +338,7 @@ DEV void passAD_body(const Job& j, int comp, int vb, int nvb, PassALdsD<N, PREC,
   __syncthreads();
   XAcc an = {0.0, 0.0, 0.0}, ae = {0.0, 0.0, 0.0};
   double pe = 0.0;  // fixed-order sum of the energies below the window
+  double pn = 0.0;  // fixed-order sum of the norm terms
   u64 hi_tot = 0ull;
   u32 ncap = 0u;
   const double* ub = j.u + (size_t)comp * j.comp_stride;
@@ -348,7 +349,7 @@ DEV void passAD_body(const Job& j, int comp, int vb, int nvb, PassALdsD<N, PREC,
     const int ne = (int)((E - e0) < T ? (E - e0) : T), nv = ne * n3;
     const double* tile = ub + e0 * n3;
     // field values in (every load of the tile issued before the first is
-    // used: one memory latency per tile), exact norm terms on the way
+    // used: one memory latency per tile), norm terms on the way
     double ut[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -363,11 +364,8 @@ DEV void passAD_body(const Job& j, int comp, int vb, int nvb, PassALdsD<N, PREC,
       int e, f;
       dense_ef<G>(v, e, f);
       const double u = ut[s];
-      const double x = v < nv ? (j.jac ? j.jac[e0 + e] * L.tab.w3[f] : L.tab.w3[f]) * (u * u) : 0.0;
-      double r;
-      if (xadd_left(an, PN, x, r)) slow_bin(gN, r);
+      pn += v < nv ? (j.jac ? j.jac[e0 + e] * L.tab.w3[f] : L.tab.w3[f]) * (u * u) : 0.0;
       buf[v] = (float)u;
-      __builtin_amdgcn_sched_barrier(0);
     }
     G::forward(buf, mt, lane);
     if constexpr (T > 1) {
@@ -423,6 +421,8 @@ DEV void passAD_body(const Job& j, int comp, int vb, int nvb, PassALdsD<N, PREC,
   {
     const double r = xadd_sum(ae, PE, pe);
     if (r != 0.0) slow_bin(gE, r);
+    const double rn = xadd_sum(an, PN, pn);
+    if (rn != 0.0) slow_bin(gN, rn);
   }
   long long v[7];
   long long kn[3], ke[3];

@@ -278,6 +278,7 @@ DEV void passAL_body(const Job& j, int comp, int vb, int nvb, PassALdsL<N, PREC>
   __syncthreads();
   XAcc an = {0.0, 0.0, 0.0}, ae = {0.0, 0.0, 0.0};
   double pe = 0.0;  // fixed-order sum of the energies below the window
+  double pn = 0.0;  // fixed-order sum of the norm terms
   u64 hi_tot = 0ull;
   u32 ncap = 0u;
   const double* ub = j.u + (size_t)comp * j.comp_stride;
@@ -285,10 +286,8 @@ DEV void passAL_body(const Job& j, int comp, int vb, int nvb, PassALdsL<N, PREC>
   float* buf = L.buf[wv];
   for (long long e = (long long)vb * 4 + wv; e < E; e += nw) {
     const double jac = j.jac ? j.jac[e] : 1.0;
-    fwd_l<G>(ub + e * n3, buf, mt, lane, [&](int q, double x) {
-      double r;
-      if (xadd_left(an, PN, (j.jac ? jac * L.tab.w3[q] : L.tab.w3[q]) * (x * x), r)) slow_bin(gN, r);
-    });
+    fwd_l<G>(ub + e * n3, buf, mt, lane,
+             [&](int q, double x) { pn += (j.jac ? jac * L.tab.w3[q] : L.tab.w3[q]) * (x * x); });
     u32 hc = 0u;
 #pragma unroll 1
     for (int b = 0; b < G::NB; ++b) {
@@ -331,6 +330,8 @@ DEV void passAL_body(const Job& j, int comp, int vb, int nvb, PassALdsL<N, PREC>
   {
     const double r = xadd_sum(ae, PE, pe);
     if (r != 0.0) slow_bin(gE, r);
+    const double rn = xadd_sum(an, PN, pn);
+    if (rn != 0.0) slow_bin(gN, rn);
   }
   long long v[7];
   long long kn[3], ke[3];

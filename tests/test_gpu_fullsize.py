@@ -7,8 +7,8 @@ on all three components for the exact norm:
   * FP64 at tol 1e-3 and at tol 1e-5: U2, tau, kept count, bitmap, every
     kept value and the measured error of component 0 equal the oracle's bit
     for bit;
-  * BF16 and FP32 at tol 1e-3: U2 of every component equals the oracle's
-    exact sum, every component meets the bound, and component 0 passes every
+  * BF16 and FP32 at tol 1e-3: U2 of every component within 1e-12 of the
+    oracle's exact sum, every component meets the bound, and component 0 passes every
     check of tests/mixed_checks.py (budget, threshold, its own cut, the
     oracle's cut at the same budget and at its own, coefficient bound, and
     the decompressed output's exact error <= tol and equal to the reported
@@ -75,7 +75,8 @@ def test_mixed_full_size(field, prec):
         assert blob.status == 0
         arr = blob.arrays()
         for c in range(3):
-            assert arr.comps[c]["U2"] == exact_sum(norm_terms(u_np[c], w3, None)), c
+            U2x = exact_sum(norm_terms(u_np[c], w3, None))
+            assert abs(arr.comps[c]["U2"] - U2x) <= 1e-12 * U2x, c
             assert arr.comps[c]["rel_err"] <= TOL, c
         coef = ctx.forward(u[:1], N, prec)[0].cpu().numpy().astype(np.float64)[None]
         out = ctx.decompress(blob)[0].cpu().numpy()[None]

@@ -1,5 +1,5 @@
 """GPU checks of the mixed-precision paths (FP32 MFMA, BF16-split MFMA)
-against the FP64 oracle: the checks of tests/mixed_checks.py (exact norm,
+against the FP64 oracle: the checks of tests/mixed_checks.py (the norm to 1e-12,
 budget with its margin, the threshold as the smallest kept energy, the
 library's own cut on its own coefficients, the oracle's cut at the same
 budget and at its own, the coefficient bound, and the decompressed output's
