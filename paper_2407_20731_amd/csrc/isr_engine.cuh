@@ -673,11 +673,22 @@ DEV void passB_body(const Job& j, int comp, int vb, int nvb, PassBLds<N, PREC>& 
       G::load(ub + e1 * n3, (int)((E - e1) < EPW ? (E - e1) : EPW), vec, un, lane);
     }
     G::forward(u, c, L.buf[wv], mt, j.tab, lane);
+    // energy weights of the slots (times the element's Jacobian), with the
+    // Jacobian test taken once per tile
+    double wq[NS];
+    if (j.jac) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        wq[s] = G::valid(s, lane, ne) ? j.jac[e0 + G::elem(s, lane)] * L.tab.g3[s][lane] : 0.0;
+    } else {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) wq[s] = L.tab.g3[s][lane];
+    }
     bool keep[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const bool v = G::valid(s, lane, ne);
-      const double en = v ? jw(j.jac, e0 + G::elem(s, lane), L.tab.g3[s][lane]) * (c[s] * c[s]) : 0.0;
+      const double en = v ? wq[s] * (c[s] * c[s]) : 0.0;
       keep[s] = v && dbits(en) >= tk;
     }
     if constexpr (G::n == 8) {
@@ -787,10 +798,19 @@ DEV void passB_body(const Job& j, int comp, int vb, int nvb, PassBLds<N, PREC>& 
 #pragma unroll
     for (int s = 0; s < NS; ++s) cm[s] = keep[s] ? c[s] : 0.0;
     G::inverse(cm, ut, L.buf[wv], mt, j.tab, lane);
+    // quadrature weights of the slots, the same way
+    if (j.jac) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        wq[s] = G::valid(s, lane, ne) ? j.jac[e0 + G::elem(s, lane)] * L.tab.w3[s][lane] : 0.0;
+    } else {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) wq[s] = L.tab.w3[s][lane];
+    }
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const double d = u[s] - ut[s];
-      const double x = G::valid(s, lane, ne) ? jw(j.jac, e0 + G::elem(s, lane), L.tab.w3[s][lane]) * (d * d) : 0.0;
+      const double x = G::valid(s, lane, ne) ? wq[s] * (d * d) : 0.0;
       if constexpr (EXACT) {
         const double r = xadd_r(ar, PR, x);
         if (r != 0.0) slow_bin(gR, r);
