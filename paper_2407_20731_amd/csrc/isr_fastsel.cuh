@@ -253,9 +253,9 @@ DEV void count_body(const Job& j, int comp, int vb, int nvb) {
 }
 
 // Element offsets from the counts, in two steps over chunks of SCAN_CHUNK
-// elements: chunk sums (the last workgroup turns them into chunk offsets and
-// checks the total against the selected kept count), then a local scan of
-// every chunk.
+// elements: chunk sums, then a local scan of every chunk on top of the sum of
+// the chunk sums before it (the last chunk's workgroup also writes the total
+// and checks it against the selected kept count).
 DEV u64 block_excl_scan(u64 v, u64* part, int tid, u64* total) {
   part[tid] = v;
   __syncthreads();
@@ -273,34 +273,9 @@ DEV u64 block_excl_scan(u64 v, u64* part, int tid, u64* total) {
 
 struct ScanLds {
   u64 part[256];
-  int last;
 };
 
-DEV void scan1_tail(const Job& j, int comp, ScanLds& X) {
-  u64* part = X.part;
-  const int tid = threadIdx.x;
-  CompState* st = j.st + comp;
-  if (st->flags & ST_MISS) return;
-  const long long E = j.n_elem;
-  const long long nch = (E + SCAN_CHUNK - 1) / SCAN_CHUNK;
-  u64* coff = j.chunk + (size_t)comp * j.nchunk;
-  // chunk sums -> exclusive chunk offsets (in place), total check
-  u64 run = 0;
-  for (long long c0 = 0; c0 < nch; c0 += 256) {
-    const long long c = c0 + tid;
-    const u64 v = c < nch ? coff[c] : 0ull;
-    u64 tot;
-    const u64 ex = block_excl_scan(v, part, tid, &tot);
-    if (c < nch) coff[c] = run + ex;
-    run += tot;
-  }
-  if (tid == 0) {
-    j.elem_ptr[(size_t)comp * (E + 1) + E] = run;
-    if (run != st->kept) atomicOr(&st->flags, ST_LIST);
-  }
-}
-
-DEV void scan1_body(const Job& j, int comp, int vb, int nvb, ScanLds& X, bool tail) {
+DEV void scan1_body(const Job& j, int comp, int vb, int nvb, ScanLds& X) {
   u64* part = X.part;
   const int tid = threadIdx.x;
   CompState* st = j.st + comp;
@@ -319,8 +294,6 @@ DEV void scan1_body(const Job& j, int comp, int vb, int nvb, ScanLds& X, bool ta
     (void)block_excl_scan(v, part, tid, &tot);
     if (tid == 0) coff[c] = tot;
   }
-  if (!tail || !last_block(j.done + D_COUNT * 8 + comp, &X.last, nvb)) return;
-  scan1_tail(j, comp, X);
 }
 
 DEV void scan2_body(const Job& j, int comp, int vb, int nvb, ScanLds& X) {
@@ -334,6 +307,11 @@ DEV void scan2_body(const Job& j, int comp, int vb, int nvb, ScanLds& X) {
   const u64* coff = j.chunk + (size_t)comp * j.nchunk;
   u64* eptr = j.elem_ptr + (size_t)comp * (E + 1);
   for (long long c = vb; c < nch; c += nvb) {
+    // the chunk's offset: the sum of the chunk sums before it
+    u64 pre = 0;
+    for (long long k = tid; k < c; k += 256) pre += coff[k];
+    u64 base;
+    (void)block_excl_scan(pre, part, tid, &base);
     // thread t owns elements c*CHUNK + 4t .. 4t+3
     const long long e0 = c * SCAN_CHUNK + 4 * tid;
     u32 v[4];
@@ -343,10 +321,14 @@ DEV void scan2_body(const Job& j, int comp, int vb, int nvb, ScanLds& X) {
       sum += v[k];
     }
     u64 tot;
-    u64 run = coff[c] + block_excl_scan(sum, part, tid, &tot);
+    u64 run = base + block_excl_scan(sum, part, tid, &tot);
     for (int k = 0; k < 4; ++k) {
       if (e0 + k < E) eptr[e0 + k] = run;
       run += v[k];
+    }
+    if (c == nch - 1 && tid == 0) {
+      eptr[E] = base + tot;
+      if (base + tot != st->kept) atomicOr(&st->flags, ST_LIST);
     }
   }
 }

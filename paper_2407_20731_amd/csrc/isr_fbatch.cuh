@@ -146,7 +146,7 @@ __device__ __noinline__ void fb_count(const Job* jr, int comp, int k, int nk) {
 }
 __device__ __noinline__ void fb_scan1(const Job* jr, int comp, int k, int nk) {
   const Job j = fb_job(jr);
-  scan1_body(j, fb_u(comp), fb_u(k), fb_u(nk), *reinterpret_cast<ScanLds*>(fb_lds), true);
+  scan1_body(j, fb_u(comp), fb_u(k), fb_u(nk), *reinterpret_cast<ScanLds*>(fb_lds));
 }
 __device__ __noinline__ void fb_scan2(const Job* jr, int comp, int k, int nk) {
   const Job j = fb_job(jr);

@@ -112,6 +112,8 @@ struct Job {
   HistBin* histNs;     // [ncomp][HBINS]  norm terms of the sampled tiles
   long long sample_stride;  // every sample_stride-th tile is sampled; 0 = no sample pass
   CompState* st;       // [ncomp]
+  CompState* hs_out;   // streaming path: device address of the request's mapped host copy of st, written by
+                       // pass B's tail; null = a separate copy kernel after the pipeline
   u64* lists;          // [ncomp][3][list_cap]
   u64 list_cap;
   // streaming path

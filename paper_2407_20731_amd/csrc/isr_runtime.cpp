@@ -543,9 +543,11 @@ static void put_host_state(isr_ctx* c, CompState* p) {
 }
 
 static int task_enqueue(Task* t) {
-  int rc = enqueue_pipeline(t->c, t->j, t->z, t->s, t->timing ? t->ev : nullptr, t->fast);
+  Job j = t->j;
+  if (!t->fast) j.hs_out = nullptr;  // the streaming path's last kernel writes the state itself
+  int rc = enqueue_pipeline(t->c, j, t->z, t->s, t->timing ? t->ev : nullptr, t->fast);
   if (rc) return rc;
-  HIPCHK(launch_state_out(t->j.st, t->hs, t->f.ncomp, t->s));
+  if (!j.hs_out) HIPCHK(launch_state_out(t->j.st, t->hs, t->f.ncomp, t->s));
   HIPCHK(hipEventRecord(t->done, t->s));
   return ISR_OK;
 }
@@ -612,6 +614,13 @@ int task_begin(isr_ctx* c, const isr_field* f, hipStream_t s, bool timing, Task*
   }
   t->j = make_job(c, f, t->z, t->scratch, blob_ptrs(t->b));
   t->j.cut_scale = t->cut_scale;
+  {
+    void* d = nullptr;
+    if (hipHostGetDevicePointer(&d, t->hs, 0) == hipSuccess)
+      t->j.hs_out = (CompState*)d;
+    else
+      (void)hipGetLastError();
+  }
   t->fast = t->z.fast;
   t->timing = timing;
   if (timing)
@@ -652,6 +661,7 @@ int task_step(Task* t, isr_blob** out) {
     double Bov[8];
     std::memcpy(Bov, t->j.Bov, sizeof(Bov));
     const long long ss = t->j.sample_stride;
+    CompState* const hs_out = t->j.hs_out;
     t->full_lists = true;
     t->c->arena->free(t->scratch);
     t->z = plan_sizes(f, t->z.tile, true);
@@ -664,6 +674,7 @@ int task_step(Task* t, isr_blob** out) {
     t->j = make_job(t->c, f, t->z, t->scratch, blob_ptrs(t->b));
     t->j.cut_scale = t->cut_scale;
     t->j.sample_stride = ss;
+    t->j.hs_out = hs_out;
     std::memcpy(t->j.Bov, Bov, sizeof(Bov));
     int rc = task_enqueue(t);
     if (rc) {

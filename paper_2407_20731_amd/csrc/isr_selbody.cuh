@@ -340,30 +340,20 @@ struct SelLds {
 };
 
 // blockDim must be 256; the sub-bin walk runs on wave 0.
-DEV void select_body(const Job& j, int comp, int L, SelLds& S) {
-  const int tid = threadIdx.x;
-  CompState* st = j.st + comp;
-  if (st->resolved) return;
-  const int ml = list_members(L);
-  __syncthreads();
-  if (st->cur_count <= (u64)CAP && (L > 2 || st->list0_exact)) {
-    resolve_sorted(j, st, comp, ml, L, S.keys, S.slo, S.shi, &S.best);
-    return;
-  }
-  if (tid >= 64) return;
-  // walk the level-L sub-bins with one wave
+// One wave walks the NB = 64 PER sub-bins of level L: lane l sums sub-bins
+// [PER l, PER l + PER), a 128-bit scan finds the lane whose chunk crosses the
+// remaining budget, and that chunk's sub-bins are loaded one per lane and
+// walked in registers.  Every load of a step is issued before any is used.
+template <int PER>
+DEV void select_walk(const Job& j, CompState* st, int comp, int L) {
   const int nb = 1 << level_bits(L), sh = level_shift(L);
   const HistBin* H = j.histL + ((size_t)(L - 2) * j.ncomp + comp) * RBINS;
-  const int per = nb >= 64 ? nb / 64 : 1;
-  const int lane = tid;
+  const int lane = lane_id();
   u128 cs = 0;
-  u64 cc = 0;
-  for (int k = 0; k < per; ++k) {
-    const int sb = lane * per + k;
-    if (sb < nb) {
-      cs += bin_sum(H[sb]);
-      cc += H[sb].cnt;
-    }
+#pragma unroll 8
+  for (int k = 0; k < PER; ++k) {
+    const int sb = lane * PER + k;
+    if (sb < nb) cs += bin_sum(H[sb]);
   }
   // inclusive scan of the lane chunk sums
   u64 ilo = (u64)cs, ihi = (u64)(cs >> 64);
@@ -393,14 +383,17 @@ DEV void select_body(const Job& j, int comp, int L, SelLds& S) {
     const u64 elo = bcast64((u64)myex, fl), ehi = bcast64((u64)(myex >> 64), fl);
     excl = ((u128)ehi << 64) | elo;
   }
+  // the crossing chunk, one sub-bin per lane, then walked in registers
+  const int msb = fl * PER + lane;
+  const HistBin mine = (lane < PER && msb < nb) ? H[msb] : HistBin{0ull, 0ull, 0ull};
   int chosen = -1;
-  for (int k = 0; k < per; ++k) {
-    const int sb = fl * per + k;
-    if (sb >= nb) break;
-    const HistBin h = H[sb];
-    if (h.cnt == 0ull) continue;
-    const u128 s = bin_sum(h);
-    chosen = sb;
+  u64 ccnt = 0ull;
+  for (int k = 0; k < PER; ++k) {
+    const u64 c = bcast64(mine.cnt, k);
+    if (c == 0ull) continue;
+    const u128 s = (((u128)bcast64(mine.hi, k)) << 21) + (u128)bcast64(mine.lo, k);
+    chosen = fl * PER + k;
+    ccnt = c;
     if (excl + s > r) break;
     excl += s;
   }
@@ -413,8 +406,9 @@ DEV void select_body(const Job& j, int comp, int L, SelLds& S) {
     return;
   }
   u64 above = 0;
-  for (int k = 0; k < per; ++k) {
-    const int sb = lane * per + k;
+#pragma unroll 8
+  for (int k = 0; k < PER; ++k) {
+    const int sb = lane * PER + k;
     if (sb < nb && sb > chosen) above += H[sb].cnt;
   }
   above = wave_sum64(above);
@@ -426,7 +420,7 @@ DEV void select_body(const Job& j, int comp, int L, SelLds& S) {
     st->w_lo = (u64)w;
     st->w_hi = (u64)(w >> 64);
     st->kept_above += above;
-    st->cur_count = H[chosen].cnt;
+    st->cur_count = ccnt;
     st->key_prefix |= (u64)chosen << sh;
     st->key_mask |= ((u64)nb - 1ull) << sh;
     st->level = L;
@@ -438,6 +432,24 @@ DEV void select_body(const Job& j, int comp, int L, SelLds& S) {
       st->list_count[list_out(L + 1)] = 0ull;
     }
   }
+}
+
+DEV void select_body(const Job& j, int comp, int L, SelLds& S) {
+  const int tid = threadIdx.x;
+  CompState* st = j.st + comp;
+  if (st->resolved) return;
+  const int ml = list_members(L);
+  __syncthreads();
+  if (st->cur_count <= (u64)CAP && (L > 2 || st->list0_exact)) {
+    resolve_sorted(j, st, comp, ml, L, S.keys, S.slo, S.shi, &S.best);
+    return;
+  }
+  if (tid >= 64) return;
+  // walk the level-L sub-bins with one wave
+  if (level_bits(L) == 11)
+    select_walk<(1 << 11) / 64>(j, st, comp, L);
+  else
+    select_walk<((1 << 8) + 63) / 64>(j, st, comp, L);
 }
 
 // --------------------------------------------------------------------------

@@ -74,23 +74,24 @@ __global__ __launch_bounds__(256) void k_count(Job j) { count_body(j, blockIdx.y
 
 __global__ __launch_bounds__(256) void k_scan1(Job j) {
   __shared__ ScanLds X;
-  scan1_body(j, blockIdx.y, blockIdx.x, gridDim.x, X, false);
+  scan1_body(j, blockIdx.y, blockIdx.x, gridDim.x, X);
 }
 
 // Per-component tails of the phases above and of the sample pass and pass B
 // (one workgroup per component, after the phase's kernel).
 __global__ __launch_bounds__(256) void k_gather_tail(Job j) { gather_tail(j, blockIdx.x); }
 
-__global__ __launch_bounds__(256) void k_scan1_tail(Job j) {
-  __shared__ ScanLds X;
-  scan1_tail(j, blockIdx.x, X);
-}
-
 __global__ __launch_bounds__(64) void k_sample_tail(Job j) { select_sample_body(j, blockIdx.x); }
 
 __global__ __launch_bounds__(256) void k_passB_tail(Job j) {
   __shared__ __int128 r3[4][3];
   passB_tail(j, blockIdx.x, r3);
+  if (j.hs_out) {  // the component's final state straight to the mapped host copy
+    __syncthreads();
+    const u64* src = (const u64*)(j.st + blockIdx.x);
+    u64* dst = (u64*)(j.hs_out + blockIdx.x);
+    for (int i = threadIdx.x; i < (int)(sizeof(CompState) / 8); i += 256) dst[i] = src[i];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_scan2(Job j) {
@@ -142,7 +143,6 @@ hipError_t launch_count(const Job& j, int gx, hipStream_t s) {
   hipLaunchKernelGGL(k_count, dim3(gx, j.ncomp), dim3(256), 0, s, j);  // independent atomics: many workgroups
   const int g = scan_grid_elems(j.n_elem);
   hipLaunchKernelGGL(k_scan1, dim3(g, j.ncomp), dim3(256), 0, s, j);
-  hipLaunchKernelGGL(k_scan1_tail, dim3(j.ncomp), dim3(256), 0, s, j);
   hipLaunchKernelGGL(k_scan2, dim3(g, j.ncomp), dim3(256), 0, s, j);
   return hipGetLastError();
 }
