@@ -50,7 +50,17 @@ struct EngD {
   static constexpr int NB = (TP + PB - 1) / PB;
   static constexpr int TV = T * n3;            // values per tile
   static constexpr int S = (TV + 63) / 64;     // dense slots per lane
-  static constexpr int LDSW = S * 64;          // floats of the wave buffer
+  static constexpr int LDSW = S * 64;          // floats of the dense slots
+  // In the passes (UM = true) rows of the contracted index past n (a0 + m >=
+  // n, when KP > n) are read without a lane mask: the A operand's columns
+  // there are zero, so whatever finite value sits at such an address adds
+  // nothing, and the lane-mask updates around every masked load go away.
+  // The farthest such read (the last pencil along k) ends before LDSB; the
+  // buffer's tail past the dense slots is zeroed once per kernel.  Stores
+  // stay masked.  The sample pass keeps masked loads and the smaller buffer
+  // (its occupancy is bound by LDS at n = 10).
+  static constexpr int OVR = T * n3 + n2 * (KP > n ? KP - n : 0);
+  static constexpr int LDSB = ((OVR > LDSW ? OVR : LDSW) + 63) / 64 * 64;  // floats of the wave buffer
   static constexpr int W = (n3 + 63) / 64;     // bitmap words per element
   static_assert(S <= 32, "dense slots per lane");
   // window candidates staged per wave in pass A (n >= 9: half, so that the
@@ -116,7 +126,7 @@ struct EngD {
   }
 
   // In-place contraction of every pencil of the tile along AX.
-  template <int AX>
+  template <int AX, bool UM>
   static DEV void stage(float* buf, const float (&f)[4], s4 h, s4 l, int lane) {
     constexpr int ST = stride<AX>();
     const int P = lane & 15, g = lane >> 4;
@@ -133,7 +143,7 @@ struct EngD {
         typedef float fl2 __attribute__((ext_vector_type(2)));
 #pragma unroll
         for (int m = 0; m < 4; m += 2) {
-          const fl2 z = (pv && a0 + m < n) ? *(const fl2*)(p + m) : fl2{0.0f, 0.0f};
+          const fl2 z = (UM || (pv && a0 + m < n)) ? *(const fl2*)(p + m) : fl2{0.0f, 0.0f};
           x[m] = z.x;
           x[m + 1] = z.y;
         }
@@ -143,7 +153,7 @@ struct EngD {
           if (pv && a0 + m < n) *(fl2*)(p + m) = fl2{y[m], y[m + 1]};
       } else {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) x[m] = (pv && a0 + m < n) ? p[m * ST] : 0.0f;
+        for (int m = 0; m < 4; ++m) x[m] = (UM || (pv && a0 + m < n)) ? p[m * ST] : 0.0f;
         mfma(x, y, f, h, l);
 #pragma unroll
         for (int m = 0; m < 4; ++m)
@@ -152,17 +162,23 @@ struct EngD {
     }
     asm volatile("" ::: "memory");
   }
+  // Zero the wave buffer's tail past the dense slots (once per kernel, before
+  // the first contraction).
+  static DEV void clear_tail(float* buf, int lane) {
+    for (int i = LDSW + lane; i < LDSB; i += 64) buf[i] = 0.0f;
+  }
+  template <bool UM = true>
   static DEV void forward(float* buf, const Mats& mt, int lane) {
     asm volatile("" ::: "memory");
-    stage<0>(buf, mt.fa, mt.ha, mt.la, lane);
-    stage<1>(buf, mt.fa, mt.ha, mt.la, lane);
-    stage<2>(buf, mt.fa, mt.ha, mt.la, lane);
+    stage<0, UM>(buf, mt.fa, mt.ha, mt.la, lane);
+    stage<1, UM>(buf, mt.fa, mt.ha, mt.la, lane);
+    stage<2, UM>(buf, mt.fa, mt.ha, mt.la, lane);
   }
   static DEV void inverse(float* buf, const Mats& mt, int lane) {
     asm volatile("" ::: "memory");
-    stage<2>(buf, mt.fv, mt.hv, mt.lv, lane);
-    stage<1>(buf, mt.fv, mt.hv, mt.lv, lane);
-    stage<0>(buf, mt.fv, mt.hv, mt.lv, lane);
+    stage<2, true>(buf, mt.fv, mt.hv, mt.lv, lane);
+    stage<1, true>(buf, mt.fv, mt.hv, mt.lv, lane);
+    stage<0, true>(buf, mt.fv, mt.hv, mt.lv, lane);
   }
 };
 
@@ -257,7 +273,7 @@ DEV void sampleD_body(const Job& j, int comp, int vb, int nvb, SampleLdsD<N, PRE
       }
       buf[v] = (float)u;
     }
-    G::forward(buf, mt, lane);
+    G::template forward<false>(buf, mt, lane);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int v = 64 * s + lane;
@@ -308,7 +324,7 @@ __global__ __launch_bounds__(256, ISR_DENSE_MINB) void k_sampleD(Job j) {
 // ---- pass A ---------------------------------------------------------------------
 template <int N, int PREC, int T>
 struct PassALdsD {
-  float buf[4][EngD<N, PREC, T>::LDSW];
+  float buf[4][EngD<N, PREC, T>::LDSB];
   TabLdsL<EngD<N, PREC, T>::n3> tab;
   u64 key[4][EngD<N, PREC, T>::CAPB];
   u32 idx[4][EngD<N, PREC, T>::CAPB];
@@ -344,6 +360,7 @@ DEV void passAD_body(const Job& j, int comp, int vb, int nvb, PassALdsD<N, PREC,
   const double* ub = j.u + (size_t)comp * j.comp_stride;
   const long long nw = (long long)nvb * 4;
   float* buf = L.buf[wv];
+  G::clear_tail(buf, lane);
   for (long long t = (long long)vb * 4 + wv; t < tiles; t += nw) {
     const long long e0 = t * T;
     const int ne = (int)((E - e0) < T ? (E - e0) : T), nv = ne * n3;
@@ -448,7 +465,7 @@ __global__ __launch_bounds__(256, (dense_minb_a<N, T>())) void k_passAD(Job j) {
 // ---- pass B ---------------------------------------------------------------------
 template <int N, int PREC, int T>
 struct PassBLdsD {
-  float buf[4][EngD<N, PREC, T>::LDSW];
+  float buf[4][EngD<N, PREC, T>::LDSB];
   TabLdsL<EngD<N, PREC, T>::n3> tab;
   u64 bal[4][EngD<N, PREC, T>::S + 1];
   u32 wc[4][T * EngD<N, PREC, T>::W];
@@ -483,6 +500,7 @@ DEV void passBD_body(const Job& j, int comp, int vb, int nvb, PassBLdsD<N, PREC,
   const double* ub = j.u + (size_t)comp * j.comp_stride;
   const long long nw = (long long)nvb * 4;
   float* buf = L.buf[wv];
+  G::clear_tail(buf, lane);
   u64* bal = L.bal[wv];
   const u64 lt = (1ull << lane) - 1ull;
   for (long long t = (long long)vb * 4 + wv; t < tiles; t += nw) {
@@ -600,11 +618,12 @@ template <int N, int PREC, int T>
 __global__ __launch_bounds__(256) void k_decompD(Job j, void* out, int out_fp64) {
   typedef EngD<N, PREC, T> G;
   constexpr int n3 = G::n3, S = G::S, W = G::W;
-  __shared__ float bufs[4][G::LDSW];
+  __shared__ float bufs[4][G::LDSB];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   typename G::Mats mt;
   G::init(mt, j.tab, lane);
   float* buf = bufs[wv];
+  G::clear_tail(buf, lane);
   const u64 lt = (1ull << lane) - 1ull;
   const long long E = j.n_elem, tiles = (E + T - 1) / T, total = tiles * j.ncomp;
   for (long long tk = (long long)blockIdx.x * 4 + wv; tk < total; tk += (long long)gridDim.x * 4) {
