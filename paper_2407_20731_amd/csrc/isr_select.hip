@@ -127,7 +127,10 @@ __global__ __launch_bounds__(256) void k_select_rest(Job j) {
 hipError_t launch_refsel(const Job& j, int gx, hipStream_t s) {
   hipLaunchKernelGGL(k_refine, dim3(gx, j.ncomp), dim3(256), 0, s, j, 2);
   hipLaunchKernelGGL(k_select, dim3(j.ncomp), dim3(256), 0, s, j, 2);
-  hipLaunchKernelGGL(k_refine, dim3(gx, j.ncomp), dim3(256), 0, s, j, 3);
+  // level 3 matches only the members of one level-2 sub-bin, so its
+  // workgroups flush few bins: more of them, for fewer list loads each
+  const int gx3 = gx * 8 < GATHER_GMAX ? gx * 8 : GATHER_GMAX;
+  hipLaunchKernelGGL(k_refine, dim3(gx3, j.ncomp), dim3(256), 0, s, j, 3);
   hipLaunchKernelGGL(k_select_rest, dim3(j.ncomp), dim3(256), 0, s, j);
   return hipGetLastError();
 }
