@@ -188,10 +188,10 @@ constexpr int dense_minb_b() {
   return N + 1 <= 7 ? 4 : ISR_DENSE_MINB;
 }
 
-// pass A launch bound of shape (N, T): four workgroups per CU (128 VGPRs,
-// a 44-byte spill) at N = 5 with tiles of up to two elements, measured 10 %
-// faster there than three; other shapes spill hundreds of bytes at 128, and
-// two workgroups at N = 9 measured 12 % slower than three
+// pass A launch bound of shape (N, T): four workgroups per CU (at most 128
+// VGPRs) at N = 5 with tiles of up to two elements, measured 10 % faster there
+// than three; larger shapes spill at 128, and two workgroups at N = 9
+// measured 12 % slower than three
 template <int N, int T>
 constexpr int dense_minb_a() {
   return (N == 5 && T <= 2) ? 4 : ISR_DENSE_MINB;

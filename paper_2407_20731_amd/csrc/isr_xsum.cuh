@@ -8,7 +8,9 @@
 // stay exact while a lane adds at most 2^(h-1) terms.  A term that leaves a
 // remainder (far below M, or above M) goes to the global exponent bins.
 // Workgroups publish the three sums as integers; the consumer adds them up
-// as 128-bit integers and writes the exact total into exponent bins.
+// as 128-bit integers and writes the exact total into exponent bins.  On the
+// FP64 path every term is split this way; on the MFMA paths a lane first adds
+// its terms in a fixed FP64 order and only that total is split (xadd_sum).
 #pragma once
 
 #include "isr_common.cuh"
