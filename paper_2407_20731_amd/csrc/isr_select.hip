@@ -143,7 +143,9 @@ hipError_t launch_gather(const Job& j, int gx, hipStream_t s) {
 }
 
 hipError_t launch_count(const Job& j, int gx, hipStream_t s) {
-  hipLaunchKernelGGL(k_count, dim3(gx, j.ncomp), dim3(256), 0, s, j);  // independent atomics: many workgroups
+  // independent atomics: many workgroups (four times the gather's; a few
+  // list loads per lane each)
+  hipLaunchKernelGGL(k_count, dim3(gx * 4, j.ncomp), dim3(256), 0, s, j);
   const int g = scan_grid_elems(j.n_elem);
   hipLaunchKernelGGL(k_scan1, dim3(g, j.ncomp), dim3(256), 0, s, j);
   hipLaunchKernelGGL(k_scan2, dim3(g, j.ncomp), dim3(256), 0, s, j);
