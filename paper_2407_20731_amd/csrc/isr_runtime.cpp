@@ -14,6 +14,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <unordered_map>
 #include <string>
 #include <thread>
 #include <vector>
@@ -125,8 +126,10 @@ struct isr_ctx {
   std::atomic<int> tile[ISR_MAX_ORDER + 1][3];  // tile shape per (order, precision); -1 = built-in
   std::string tune_path;           // tile table file (read at create, written by the autotuner)
   CompState* st_host = nullptr;  // pinned state copy of isr_compress_noalloc (under mu)
-  std::mutex host_mu;            // pool of pinned per-request state buffers
+  std::mutex host_mu;            // pools of pinned per-request state buffers and completion events
   std::vector<CompState*> host_all, host_free;
+  std::unordered_map<CompState*, CompState*> host_dev;  // device address of each state buffer (null: none)
+  std::vector<hipEvent_t> ev_all, ev_free;
 };
 
 static int set_device(isr_ctx* c) {
@@ -529,6 +532,12 @@ static CompState* grab_host_state(isr_ctx* c) {
       return nullptr;
     }
     c->host_all.push_back(p);
+    void* d = nullptr;
+    if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      d = nullptr;
+    }
+    c->host_dev[p] = (CompState*)d;
     return p;
   }
   CompState* p = c->host_free.back();
@@ -540,6 +549,36 @@ static void put_host_state(isr_ctx* c, CompState* p) {
   if (!p) return;
   std::lock_guard<std::mutex> g(c->host_mu);
   c->host_free.push_back(p);
+}
+
+static CompState* host_state_dev(isr_ctx* c, CompState* p) {
+  std::lock_guard<std::mutex> g(c->host_mu);
+  auto it = c->host_dev.find(p);
+  return it == c->host_dev.end() ? nullptr : it->second;
+}
+
+// Completion events are reused across requests (creating one per request
+// costs host time between back-to-back requests).
+static hipEvent_t grab_event(isr_ctx* c) {
+  std::lock_guard<std::mutex> g(c->host_mu);
+  if (c->ev_free.empty()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    c->ev_all.push_back(e);
+    return e;
+  }
+  hipEvent_t e = c->ev_free.back();
+  c->ev_free.pop_back();
+  return e;
+}
+
+static void put_event(isr_ctx* c, hipEvent_t e) {
+  if (!e) return;
+  std::lock_guard<std::mutex> g(c->host_mu);
+  c->ev_free.push_back(e);
 }
 
 static int task_enqueue(Task* t) {
@@ -560,7 +599,7 @@ void task_release(Task* t) {
     delete t->b;
     t->b = nullptr;
   }
-  if (t->done) (void)hipEventDestroy(t->done);
+  put_event(t->c, t->done);
   t->done = nullptr;
   if (t->timing)
     for (auto& e : t->ev) (void)hipEventDestroy(e);
@@ -608,19 +647,13 @@ int task_begin(isr_ctx* c, const isr_field* f, hipStream_t s, bool timing, Task*
     return fail(ISR_ENOMEM, "blob of %zu bytes does not fit the HBM budget", t->z.blob_max);
   }
   t->hs = grab_host_state(c);
-  if (!t->hs || hipEventCreateWithFlags(&t->done, hipEventDisableTiming) != hipSuccess) {
+  if (!t->hs || !(t->done = grab_event(c))) {
     task_release(t);
     return fail(ISR_EDEVICE, "could not create host state or event");
   }
   t->j = make_job(c, f, t->z, t->scratch, blob_ptrs(t->b));
   t->j.cut_scale = t->cut_scale;
-  {
-    void* d = nullptr;
-    if (hipHostGetDevicePointer(&d, t->hs, 0) == hipSuccess)
-      t->j.hs_out = (CompState*)d;
-    else
-      (void)hipGetLastError();
-  }
+  t->j.hs_out = host_state_dev(c, t->hs);
   t->fast = t->z.fast;
   t->timing = timing;
   if (timing)
@@ -1284,6 +1317,7 @@ int isr_destroy(isr_ctx* c) {
   if (c->tables_dev) (void)hipFree(c->tables_dev);
   if (c->st_host) (void)hipHostFree(c->st_host);
   for (CompState* p : c->host_all) (void)hipHostFree(p);
+  for (hipEvent_t e : c->ev_all) (void)hipEventDestroy(e);
   delete c;
   return ISR_OK;
 }
