@@ -303,7 +303,6 @@ DEV void sampleD_body(const Job& j, int comp, int vb, int nvb, SampleLdsD<N, PRE
   HistBin* H = j.histEs + (size_t)comp * HBINS;
   for (int k = tid; k < SBINS; k += 256) {
     if (L.hc[k]) {
-      atomicAdd(&H[k].cnt, (u64)L.hc[k]);
       atomicAdd((double*)&H[k].lo, ldexp((double)L.hs[k], k - 1023));
     }
   }

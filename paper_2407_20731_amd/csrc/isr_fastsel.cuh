@@ -39,14 +39,12 @@ DEV void select_sample_body(const Job& j, int comp) {
     return;
   }
   const double B = ((tol * tol) * st->samp_u2) * j.cut_scale;
+  // (the sampled bins hold rounded sums only: one atomic per bin and
+  // workgroup, and a bin of positive energies has a positive sum)
   double cs = 0.0;
-  u64 cc = 0;
   for (int k = 0; k < 32; ++k) {
     const int b = 32 * lane + k;
-    if (b < HBINS - 1) {
-      cs += __longlong_as_double((long long)H[b].lo);
-      cc += H[b].cnt;
-    }
+    if (b < HBINS - 1) cs += __longlong_as_double((long long)H[b].lo);
   }
   double incl = cs;
   for (int d = 1; d < 64; d <<= 1) {
@@ -54,7 +52,7 @@ DEV void select_sample_body(const Job& j, int comp) {
     if (lane >= d) incl += o;
   }
   const u64 over = ballot(incl > B);
-  const u64 nonempty = ballot(cc != 0ull);
+  const u64 nonempty = ballot(cs > 0.0);
   int bstar = -1;
   if (over) {
     const int fl = __ffsll((long long)over) - 1;
@@ -74,7 +72,7 @@ DEV void select_sample_body(const Job& j, int comp) {
     const int fl = 63 - __clzll((long long)nonempty);
     for (int k = 31; k >= 0; --k) {
       const int b = 32 * fl + k;
-      if (b < HBINS - 1 && H[b].cnt) {
+      if (b < HBINS - 1 && __longlong_as_double((long long)H[b].lo) > 0.0) {
         bstar = b;
         break;
       }
